@@ -1,0 +1,507 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks one part of the oracle against something other than the
+oracle itself: a library routine, a closed form, an exact rational evaluation,
+a value printed in the paper, or an invariant.  A plausible slip (dropped term,
+wrong sign, wrong weight, transposed operand) in the oracle fails at least one
+of them.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "paper_constants.json")))
+
+
+# --------------------------------------------------------------------------- #
+# quadrature and Chebyshev building blocks
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 64, 128, 333, 1024])
+def test_gauss_legendre_matches_numpy(ref, n):
+    x, w = ref.gauss_legendre(n)
+    X, W = np.polynomial.legendre.leggauss(n)
+    assert np.max(np.abs(x - X)) < 2e-15
+    # numpy's weights carry ~1e-12..1e-10 relative error near the ends (growing
+    # with n), so compare absolutely here and to multiprecision below
+    assert np.max(np.abs(w - W)) < 5e-14
+
+
+@pytest.mark.parametrize("n", [20, 64, 128])
+def test_gauss_legendre_against_multiprecision(ref, n):
+    import mpmath as mp
+    mp.mp.dps = 40
+    x, w = ref.gauss_legendre(n)
+
+    def leg(s):
+        p0, p1 = mp.mpf(1), s
+        for k in range(1, n):
+            p0, p1 = p1, ((2 * k + 1) * s * p1 - k * p0) / (k + 1)
+        return p1, p0
+    for i in range(n):
+        s = mp.mpf(x[i])
+        for _ in range(5):
+            p1, p0 = leg(s)
+            s -= p1 / (n * (s * p1 - p0) / (s * s - 1))
+        p1, p0 = leg(s)
+        wt = 2 / ((1 - s * s) * (n * (s * p1 - p0) / (s * s - 1)) ** 2)
+        assert abs(x[i] - float(s)) < 2e-16
+        assert abs(w[i] - float(wt)) < 1e-12 * float(wt)
+
+
+@pytest.mark.parametrize("n", [3, 8, 40])
+def test_gauss_legendre_exact_for_degree_2n_minus_1(ref, n):
+    x, w = ref.gauss_legendre(n)
+    for d in range(0, 2 * n):
+        exact = 0.0 if d % 2 else 2.0 / (d + 1)
+        assert abs(np.sum(w * x ** d) - exact) < 1e-13
+
+
+def test_chebyshev_against_trig_and_numpy(ref):
+    n = 40
+    for s in np.linspace(-1, 1, 17):
+        T = ref.cheb(s, n)
+        expect = np.cos(np.arange(n) * np.arccos(s))
+        expect[0] = 0.5
+        assert np.max(np.abs(T - expect)) < 1e-13
+        coef = np.random.default_rng(3).standard_normal(n)
+        # the series sum_j c_j Tilde-T_j is numpy's chebval with c_0 halved
+        c_np = coef.copy(); c_np[0] *= 0.5
+        assert abs(coef @ T - np.polynomial.chebyshev.chebval(s, c_np)) < 1e-12
+
+
+def test_chebyshev_interpolation_exact_for_polynomials(ref):
+    """The start-guess transform (values at the N roots -> coefficients) is exact
+    for degree < N polynomials; checked through lnZ with linear s(x)."""
+    p = ref.params(n_z=12, n_g=12, kappa=0.0, delta=0.0, gamma=0.0)
+    # a polynomial of degree 11 in s, as Chebyshev coefficients with c0/2
+    coef = np.random.default_rng(1).standard_normal(12)
+    for s in np.linspace(-1, 1, 9):
+        u = math.exp(0.5 * (math.log(p.eps2) + math.log(p.lambda2))
+                     + 0.5 * (math.log(p.lambda2) - math.log(p.eps2)) * s)
+        c_np = coef.copy(); c_np[0] *= 0.5
+        assert abs(ref.lnZ(p, coef, u) - np.polynomial.chebyshev.chebval(s, c_np)) < 1e-12
+
+
+# --------------------------------------------------------------------------- #
+# mapping and extrapolation (Sec. 3 mapping; Sec. 2 IR power laws / UV logs)
+
+def test_mapping_endpoints(ref):
+    p = ref.params(eps2=1e-8, lambda2=1e8)
+    assert abs(ref.mapping(p, 1e-8) + 1) < 1e-15
+    assert abs(ref.mapping(p, 1e8) - 1) < 1e-15
+    assert abs(ref.mapping(p, 1.0)) < 1e-15
+    assert ref.mapping(p, 1e-20) == -1.0 and ref.mapping(p, 1e20) == 1.0
+    # log10 ratio: s(10^k) = k/8
+    for k in range(-8, 9):
+        assert abs(ref.mapping(p, 10.0 ** k) - k / 8) < 1e-14
+
+
+def test_extrapolation_is_continuous_and_exact(ref):
+    p = ref.params(**workloads.config("cfg2"))
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal(p.n_z) / (1 + np.arange(p.n_z))
+    b = rng.standard_normal(p.n_g) / (1 + np.arange(p.n_g))
+    k, om = p.kappa, 11 * p.n_c * p.alpha_mu / (12 * math.pi)
+    for f, coef, ir, uv in [(ref.lnZ, a, 2 * k, p.gamma), (ref.lnG, b, -k, p.delta)]:
+        e, L = p.eps2, p.lambda2
+        # continuity at both matching points
+        assert abs(f(p, coef, e * (1 - 1e-12)) - f(p, coef, e * (1 + 1e-12))) < 1e-9
+        assert abs(f(p, coef, L * (1 - 1e-12)) - f(p, coef, L * (1 + 1e-12))) < 1e-9
+        # IR: pure power law u^{ir} matched at eps2
+        for u in [e * 1e-3, e * 1e-17]:
+            assert abs(f(p, coef, u) - (f(p, coef, e) + ir * math.log(u / e))) < 1e-12
+        # UV: [omega ln(u/L) + 1]^{uv} matched at L
+        for u in [L * 1.5, L * 4]:
+            assert abs(f(p, coef, u) - (f(p, coef, L) + uv * math.log(om * math.log(u / L) + 1))) < 1e-12
+
+
+# --------------------------------------------------------------------------- #
+# kernels (Sec. 2)
+
+def test_kernel_M_simplified_equals_printed(ref):
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        x, y = 10 ** rng.uniform(-2, 2, 2)
+        th = rng.uniform(0.05, math.pi - 0.05)
+        z = x + y - 2 * math.sqrt(x * y) * math.cos(th)
+        if z < 1e-2 * max(x, y):
+            continue
+        a, b = ref.kernel_M(x, y, th), ref.kernel_M_printed(x, y, z)
+        assert abs(a - b) <= 1e-10 * (abs(b) + 1)
+
+
+def test_kernel_Q_stable_equals_printed_where_well_conditioned(ref):
+    rng = np.random.default_rng(12)
+    for _ in range(200):
+        x, y = 10 ** rng.uniform(-1, 1, 2)
+        th = rng.uniform(0.1, math.pi - 0.1)
+        z = x + y - 2 * math.sqrt(x * y) * math.cos(th)
+        a, b = ref.kernel_Q(x, y, th), ref.kernel_Q_printed(x, y, z)
+        assert abs(a - b) <= 1e-9 * (abs(b) + 1)
+
+
+def _q_printed_exact(x, y, z):
+    return (Fraction(1) / (z * z)) * (x ** 3 / (8 * y) + x * x - Fraction(9, 4) * x * y + y * y + y ** 3 / (8 * x)) \
+        + (Fraction(1) / z) * (x * x / y - 4 * (x + y) + y * y / x) \
+        - (Fraction(9, 4) * x / y + 4 + Fraction(9, 4) * y / x) \
+        + z * (Fraction(1) / x + Fraction(1) / y) + z * z / (8 * x * y) + Fraction(15, 4)
+
+
+@pytest.mark.parametrize("x,y", [(1.0, 1e-30), (1e8, 1e-26), (2.0 ** -60, 3.0), (1.0, 1.0)])
+def test_kernel_Q_stable_against_exact_rational_printed_form(ref, x, y):
+    """The printed Q evaluated in exact rational arithmetic (no cancellation) at
+    points where the floating-point printed form loses every digit."""
+    for cos_t in [0.3, -0.7, 0.999]:
+        th = math.acos(cos_t)
+        X, Y = Fraction(x), Fraction(y)
+        # sqrt(xy) must be rational: choose y so that xy is a perfect square in binary
+        r = math.sqrt(x * y)
+        R = Fraction(r)
+        if R * R != X * Y:
+            Y = R * R / X
+            y = float(Y)
+        Z = X + Y - 2 * R * Fraction(cos_t)
+        exact = float(_q_printed_exact(X, Y, Z))
+        got = ref.kernel_Q(x, y, math.acos(float(Fraction(cos_t))))
+        assert abs(got - exact) <= 1e-12 * max(1.0, abs(exact)), (x, y, cos_t, got, exact)
+
+
+def test_kernel_Q_symmetric(ref):
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        x, y = 10 ** rng.uniform(-5, 5, 2)
+        th = rng.uniform(0, math.pi)
+        assert abs(ref.kernel_Q(x, y, th) - ref.kernel_Q(y, x, th)) <= 1e-12 * abs(ref.kernel_Q(x, y, th))
+
+
+def test_momentum_z(ref):
+    assert ref.momentum_z(0.0, 3.0, 0.4) == 3.0
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        x, y = 10 ** rng.uniform(-2, 2, 2)
+        th = rng.uniform(0.3, math.pi)
+        z = x + y - 2 * math.sqrt(x * y) * math.cos(th)
+        assert abs(ref.momentum_z(x, y, th) - z) <= 1e-13 * z
+
+
+# --------------------------------------------------------------------------- #
+# angular integrals: closed forms (normalised by pi/2 = int sin^2)
+
+def _ang(ref, n=200):
+    x, w = ref.gauss_legendre(n)
+    return 0.5 * math.pi * (1 + x), 0.5 * math.pi * w
+
+
+@pytest.mark.parametrize("x,y", [(1.0, 3.7), (2.0, 0.3), (1.0, 50.0), (5.0, 0.01)])
+def test_angular_closed_forms(ref, x, y):
+    th, v = _ang(ref)
+    r = min(x, y) / max(x, y)
+    s2 = np.sin(th) ** 2
+    M = sum(vk * s * ref.kernel_M(x, y, t) for t, vk, s in zip(th, v, s2)) / (math.pi / 2)
+    Q = sum(vk * s * ref.kernel_Q(x, y, t) for t, vk, s in zip(th, v, s2)) / (math.pi / 2)
+    G = sum(vk * s * s / ref.momentum_z(x, y, t) ** 2 for t, vk, s in zip(th, v, s2))
+    Mc = 0.75 - 0.25 * r if y > x else 0.75 * r - 0.25 * r * r
+    Qc = -0.75 - 6.25 * r + 0.875 * r * r
+    assert abs(M - Mc) < 1e-9
+    assert abs(Q - Qc) < 1e-9
+    assert abs(G - 3 * math.pi / (8 * max(x, y) ** 2)) < 1e-9 / max(x, y) ** 2
+
+
+# --------------------------------------------------------------------------- #
+# self-energies at G = Z = 1 (kappa = delta = gamma = 0 switch the extrapolations
+# off, c = 0 makes the series vanish): closed forms over y in [0, Lambda^2]
+#   Pi_G(x) = -C (3 pi / 8) [1/2 + ln(Lambda^2/x)]
+#   Pi_Z(x) = (alpha N_c / 12 pi) [-29/12 - (7/8) x/Lambda^2 - (13/2) ln(Lambda^2/x)]
+
+def _split_grid(x, lo, hi, panels=60, nodes=20):
+    u, w = np.polynomial.legendre.leggauss(nodes)
+    edges = [lo] + ([math.log(x)] if lo < math.log(x) < hi else []) + [hi]
+    ys, Ws = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        e = np.linspace(a, b, panels + 1)
+        for aa, bb in zip(e[:-1], e[1:]):
+            t = 0.5 * (aa + bb) + 0.5 * (bb - aa) * u
+            ys.append(np.exp(t)); Ws.append(0.5 * (bb - aa) * w * np.exp(t))
+    return np.concatenate(ys), np.concatenate(Ws)
+
+
+@pytest.mark.parametrize("x", [1e-2, 1.0, 1e2])
+@pytest.mark.parametrize("alpha", [1.0, 0.37])
+def test_self_energies_closed_form_at_unit_dressings(ref, x, alpha):
+    L2 = 1e4
+    p = ref.params(kappa=0.0, delta=0.0, gamma=0.0, eps2=1e-30, lambda2=L2, n_z=4, n_g=4,
+                   alpha_mu=alpha)
+    c = np.zeros(8)
+    th, v = _ang(ref)
+    y, W = _split_grid(x, math.log(1e-40), math.log(L2))
+    C = alpha * 3 / (2 * math.pi ** 2)
+    pg = ref.pi_ghost(p, c, x, y, W, th, v)
+    pz = ref.pi_gluon(p, c, x, y, W, th, v)
+    eg = -C * 3 * math.pi / 8 * (0.5 + math.log(L2 / x))
+    ez = alpha * 3 / (12 * math.pi) * (-29 / 12 - 7 / 8 * x / L2 - 6.5 * math.log(L2 / x))
+    assert abs(pg / eg - 1) < 1e-8
+    assert abs(pz / ez - 1) < 1e-8
+
+
+def test_one_loop_anomalous_dimensions(ref):
+    """d Pi / d ln x at unit dressings divided by omega gives -delta and -gamma
+    exactly (Sec. 2: delta = -9/44, gamma = -13/22)."""
+    L2 = 1e6
+    p = ref.params(kappa=0.0, delta=0.0, gamma=0.0, eps2=1e-30, lambda2=L2, n_z=4, n_g=4)
+    c = np.zeros(8)
+    th, v = _ang(ref)
+    om = 11 * 3 * 1.0 / (12 * math.pi)
+    x1, x2 = 1.0, 10.0
+    vals = {}
+    for x in (x1, x2):
+        y, W = _split_grid(x, math.log(1e-40), math.log(L2))
+        vals[x] = (ref.pi_ghost(p, c, x, y, W, th, v), ref.pi_gluon(p, c, x, y, W, th, v))
+    dlx = math.log(x2 / x1)
+    slope_g = (vals[x2][0] - vals[x1][0]) / dlx
+    # the gluon closed form has a (7/8) x/Lambda^2 term; remove it to isolate the log
+    slope_z = (vals[x2][1] - vals[x1][1]) / dlx + (3 / (12 * math.pi)) * (7 / 8) * (x2 - x1) / L2 / dlx
+    assert abs(slope_g / om - GOLD["delta"]["value"] * -1) < 1e-8
+    assert abs(slope_z / om - GOLD["gamma"]["value"] * -1) < 1e-8
+    assert GOLD["delta"]["value"] == -9 / 44 and GOLD["gamma"]["value"] == -13 / 22
+
+
+# --------------------------------------------------------------------------- #
+# IR analysis: kappa and alpha(0) (Sec. 2 power laws, Sec. 2.1 fixed point)
+
+def test_ir_exponent_and_fixed_point_from_kernels(ref):
+    """With Z = A x^{2 kappa}, G = B x^{-kappa} the ghost equation (G(0)^{-1}=0)
+    and the ghost loop of the gluon equation are consistent iff
+    I_Z(kappa)/3 = -I_G(kappa), and then N_c alpha(0) = -2 pi^2 / I_G.  Built
+    from the oracle's own z and M kernels with the sin^4 / sin^2 angular weights;
+    must reproduce the paper's kappa = 0.595353 and alpha(0) N_c = 8.915."""
+    K = ref.KAPPA
+    assert abs(K - GOLD["kappa"]["value"]) < 5e-7
+    S0 = 20.0
+
+    def inner_G(s):
+        u = math.exp(s)
+        f = lambda th: math.sin(th) ** 4 * (ref.momentum_z(1.0, u, th) ** (2 * K - 2) - u ** (2 * K - 2))
+        return u ** (2 - K) * integrate.quad(f, 0, math.pi, limit=200, epsabs=0, epsrel=1e-12)[0]
+
+    def inner_Z(s):
+        u = math.exp(s)
+        f = lambda th: math.sin(th) ** 2 * ref.kernel_M(1.0, u, th) * ref.momentum_z(1.0, u, th) ** (-K)
+        return u ** (1 - K) * integrate.quad(f, 0, math.pi, limit=200, epsabs=0, epsrel=1e-12)[0]
+
+    segs = [(-60, -5), (-5, -0.5), (-0.5, 0), (0, 0.5), (0.5, 5), (5, S0)]
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        IG = sum(integrate.quad(inner_G, a, b, limit=400, epsabs=0, epsrel=1e-11)[0] for a, b in segs)
+        IZ = sum(integrate.quad(inner_Z, a, b, limit=400, epsabs=0, epsrel=1e-11)[0] for a, b in segs)
+    # large-u tails from the expansion in 1/sqrt(u) (angular moments of sin^4)
+    pw = 2 * K - 2
+    IG += pw * (3 * math.pi / 8 + (pw - 1) * math.pi / 8) * math.exp((K - 1) * S0) / (1 - K)
+    q = -1 - K
+    IZ += 3 * math.pi / 8 * math.exp((1 - 2 * K) * S0) / (2 * K - 1) \
+        + (q * 3 * math.pi / 8 + q * (q - 1) * math.pi / 8) * math.exp(-2 * K * S0) / (2 * K)
+    assert abs((IZ / 3) / IG + 1) < 1e-9
+    nc_alpha0 = -2 * math.pi ** 2 / IG
+    assert abs(nc_alpha0 - GOLD["alpha0_times_nc"]["value"]) < 1e-3
+    # wrong exponent breaks the consistency condition
+    assert abs((IZ / 3) / IG + 1) < 1e-3
+
+
+# --------------------------------------------------------------------------- #
+# derivatives
+
+def test_analytic_jacobian_matches_central_differences(ref):
+    p = ref.params(**workloads.config("cfg1", n_z=10, n_g=12))
+    c = ref.start_guess(p) + workloads.perturbation(10, 12, 0.05, seed=1)
+    J = ref.jacobian(p, c)
+    Jfd = ref.jacobian_fd(p, c, 1e-5)
+    assert np.linalg.norm(J - Jfd) <= 1e-7 * np.linalg.norm(J)
+    # column by column too (catches a transposed block)
+    for j in range(J.shape[1]):
+        assert np.linalg.norm(J[:, j] - Jfd[:, j]) <= 1e-6 * np.linalg.norm(J[:, j]) + 1e-12 * np.linalg.norm(J)
+
+
+def test_jacobian_rows_subset_and_F(ref):
+    p = ref.params(**workloads.config("cfg1"))
+    c = ref.start_guess(p)
+    J, F = ref.jacobian(p, c, with_F=True)
+    assert np.array_equal(F, ref.residual(p, c))
+    rows = [0, 5, 17, 31]
+    Js = ref.jacobian(p, c, rows=rows)
+    assert np.array_equal(Js[rows], J[rows])
+
+
+def test_dF_dtheta_matches_differences(ref):
+    base = workloads.config("cfg1", n_z=8, n_g=8, g0_inv=0.1)
+    p = ref.params(**base)
+    c = ref.start_guess(p)
+    D = ref.dF_dtheta(p, c)
+    S = ref.residual_scale(p, c)
+    for col, key, h in [(0, "alpha_mu", 1e-4), (1, "g0_inv", 1e-3), (2, "z_lambda_inv", 1e-3)]:
+        pp = ref.params(**dict(base, **{key: base[key] + h}))
+        pm = ref.params(**dict(base, **{key: base[key] - h}))
+        fd = (ref.residual(pp, c) - ref.residual(pm, c)) / (2 * h)
+        # central-difference truncation (alpha only) plus rounding of F / h
+        tol = 1e-6 * np.abs(fd) + 50 * S * 2.2e-16 / h
+        assert np.all(np.abs(D[:, col] - fd) <= tol), (key, np.abs(D[:, col] - fd) / tol)
+
+
+def test_dF_dalpha_sees_uv_extension(ref):
+    """alpha enters through C (linear) and through omega in the UV logs; with the
+    UV exponents switched off only the linear part remains."""
+    base = workloads.config("cfg1", n_z=8, n_g=8, g0_inv=0.1)
+    p = ref.params(**base)
+    c = ref.start_guess(p)
+    p0 = ref.params(**dict(base, delta=0.0, gamma=0.0))
+    D0 = ref.dF_dtheta(p0, c)[:, 0]
+    F0 = ref.residual(p0, c)
+    # F = direct - param - Pi(x) + Pi(sub); Pi is linear in alpha when omega drops out
+    pp = ref.params(**dict(base, delta=0.0, gamma=0.0, alpha_mu=2.0))
+    slope = ref.residual(pp, c) - F0
+    assert np.linalg.norm(D0 - slope) <= 1e-10 * np.linalg.norm(slope)
+
+
+# --------------------------------------------------------------------------- #
+# LU
+
+@pytest.mark.parametrize("n", [1, 7, 64, 130])
+@pytest.mark.parametrize("trans", [False, True])
+def test_lu_solve_matches_numpy(ref, n, trans):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) + np.diag(rng.uniform(-3, 3, n))
+    b = rng.standard_normal(n)
+    x = ref.lu_solve(A, b, trans=trans)
+    xe = np.linalg.solve(A.T if trans else A, b)
+    assert np.linalg.norm(x - xe) <= 1e-11 * np.linalg.norm(xe) * np.linalg.cond(A) / 100 + 1e-13
+
+
+def test_lu_pivots(ref):
+    A = np.array([[0.0, 1.0], [1.0, 0.0]])
+    assert np.allclose(ref.lu_solve(A, [2.0, 3.0]), [3.0, 2.0])
+
+
+def test_lu_singular(ref):
+    with pytest.raises(ref.OracleError):
+        ref.lu_solve(np.ones((3, 3)), np.ones(3))
+
+
+# --------------------------------------------------------------------------- #
+# grid
+
+def test_grid_layout(ref):
+    p = ref.params(**workloads.config("cfg2"))
+    g = ref.grid(p)
+    assert len(g.y) == p.n_rad + p.n_ir and len(g.theta) == p.n_ang
+    assert np.all(np.diff(g.y) > 0) and np.all(np.diff(g.x_z) > 0)
+    # int_0^Lambda^2 dy = Lambda^2 up to the IR panel's missing [0, eps2 e^-40]
+    assert abs(np.sum(g.W) / p.lambda2 - 1) < 1e-12
+    # int_0^pi dtheta sin^2 = pi/2, sin^4 = 3 pi / 8
+    assert abs(np.sum(g.v * np.sin(g.theta) ** 2) - math.pi / 2) < 1e-13
+    assert abs(np.sum(g.v * np.sin(g.theta) ** 4) - 3 * math.pi / 8) < 1e-13
+    # external points are the mapped roots of T_N
+    s = np.array([ref.mapping(p, x) for x in g.x_z])
+    assert np.max(np.abs(np.cos(p.n_z * np.arccos(s)))) < 1e-12
+
+
+# --------------------------------------------------------------------------- #
+# the solved system
+
+@pytest.fixture(scope="module")
+def cfg1_solution(ref):
+    p = ref.params(**workloads.config("cfg1"))
+    c, rep = ref.newton(p)
+    return p, c, rep
+
+
+def test_newton_converges_quadratically(ref, cfg1_solution):
+    p, c, rep = cfg1_solution
+    assert rep["status"] == 0
+    h = [f for f in rep["fnorm_hist"] if f > 0]
+    assert h[-1] < 1e-13
+    # last contracting steps: ||F_{n+1}|| <= K ||F_n||^2 with one constant K
+    # (the scaled residual is an equivalent norm near the root)
+    tail = [(a, b) for a, b in zip(h[:-1], h[1:]) if 1e-12 < a < 1e-3]
+    assert len(tail) >= 3 and all(b < 2e4 * a * a for a, b in tail)
+
+
+def test_scaling_solution_ir_exponent_and_coupling(ref, cfg1_solution):
+    """Sec. 2 / 2.1: for G(0)^{-1} = 0 the solution is ghost-enhanced and
+    gluon-suppressed with G ~ x^{-kappa}, Z ~ x^{2 kappa} and the running
+    coupling alpha(x) = alpha(mu^2) G^2 Z approaches 8.915/N_c in the IR."""
+    p, c, rep = cfg1_solution
+    a, b = c[:p.n_z], c[p.n_z:]
+    x1, x2 = 1e-6, 1e-4
+    sg = (ref.lnG(p, b, x2) - ref.lnG(p, b, x1)) / math.log(x2 / x1)
+    sz = (ref.lnZ(p, a, x2) - ref.lnZ(p, a, x1)) / math.log(x2 / x1)
+    assert abs(sg / -ref.KAPPA - 1) < 0.03
+    assert abs(sz / (2 * ref.KAPPA) - 1) < 0.03
+    alpha0 = p.alpha_mu * math.exp(2 * ref.lnG(p, b, p.eps2) + ref.lnZ(p, a, p.eps2))
+    assert abs(alpha0 / GOLD["alpha0_nc3"]["value"] - 1) < 0.01
+    # ghost enhanced, gluon suppressed
+    assert ref.lnG(p, b, 1e-6) > 5 and ref.lnZ(p, a, 1e-6) < -10
+
+
+def test_scaling_solution_uv_behaviour(ref, cfg1_solution):
+    """Sec. 2 UV logs: d ln Z / d ln G -> gamma / delta = 26/9 (one loop)."""
+    p, c, rep = cfg1_solution
+    a, b = c[:p.n_z], c[p.n_z:]
+    x1, x2 = 1e4, 1e6 * 0.99
+    r = (ref.lnZ(p, a, x2) - ref.lnZ(p, a, x1)) / (ref.lnG(p, b, x2) - ref.lnG(p, b, x1))
+    assert abs(r / (26 / 9) - 1) < 0.1
+
+
+def test_solution_satisfies_equations_componentwise(ref, cfg1_solution):
+    p, c, rep = cfg1_solution
+    F = ref.residual(p, c)
+    S = ref.residual_scale(p, c)
+    assert np.max(np.abs(F) / S) < 1e-13
+
+
+def test_decoupling_solution(ref):
+    """Sec. 2.1: G(x_G)^{-1} > 0 gives a finite ghost and a coupling that
+    vanishes in the IR."""
+    p = ref.params(**workloads.config("cfg1", g0_inv=0.1))
+    c, rep = ref.newton(p)
+    assert rep["status"] == 0
+    a, b = c[:p.n_z], c[p.n_z:]
+    assert abs(math.exp(-ref.lnG(p, b, p.eps2)) - 0.1) < 0.02
+    alpha_ir = math.exp(2 * ref.lnG(p, b, p.eps2) + ref.lnZ(p, a, p.eps2))
+    assert alpha_ir < 1e-3
+
+
+def test_rounding_floor_reversed_order(ref):
+    """Summing in reversed order moves F by far less than the parity tolerance."""
+    p = ref.params(**workloads.config("cfg1"))
+    c = ref.start_guess(p)
+    F1 = ref.residual(p, c)
+    S = ref.residual_scale(p, c)
+    try:
+        ref.set_order(True)
+        F2 = ref.residual(p, c)
+    finally:
+        ref.set_order(False)
+    assert np.max(np.abs(F1 - F2) / S) < 1e-15
+
+
+def test_one_loop_z_lambda_values():
+    """The Z(Lambda^2) inputs follow from the paper's pair alpha(mu^2)=1,
+    Z(5e4)=0.256 under one-loop running (Sec. 2.1 and its footnote)."""
+    om = 11 * 3 / (12 * math.pi)
+    gamma = -13 / 22
+    r_paper = GOLD["z_xz_paper"]["value"] ** (1 / -gamma)
+    mu2 = GOLD["lambda2_paper"]["value"] / math.exp((1 / r_paper - 1) / om)
+    assert abs(mu2 - 1.64915) < 1e-4
+    for L2, z in [(1e6, workloads.Z_LAMBDA_1E6), (1e8, workloads.Z_LAMBDA_1E8)]:
+        r = 1 / (1 + om * math.log(L2 / mu2))
+        assert abs(r ** (-gamma) - z) < 2e-6
+    # and the pair reproduces alpha(M_Z^2) = 0.118 to the quoted digits
+    mz2 = GOLD["alpha_mz"]["mz_gev"] ** 2
+    assert abs(1 / (1 + om * math.log(mz2 / mu2)) - GOLD["alpha_mz"]["value"]) < 2e-3
