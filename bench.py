@@ -1,0 +1,155 @@
+"""Benchmark of the ghost-gluon DSE hot path on one MI355X.
+
+A step is one Newton iteration of the N = 64 workload (64 Chebyshev
+coefficients per dressing function, 256+64 radial x 64 angular quadrature,
+decoupling G(0) = 15): Newton matrix and residual assembly (dressing, fused
+point kernels, B.T contraction on MFMA, assembly), the FP64 LU solve of
+J Delta = F, and the residual at c - Delta.  value = Newton-matrix entries
+(n^2 = 128^2) per second of step time.
+
+Prints one JSON line (rank 0).  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+GLUON_SCALAR_FLOPS = 100        # per gluon point, besides the Chebyshev work
+GHOST_SCALAR_FLOPS = 60
+
+
+def gluon_point_flops(cfg: dict) -> float:
+    """Algorithmic flops of one launch of the gluon point kernel (Jacobian mode):
+    per point (row, radial node, angle) the recurrence 2 max(N), the two series
+    and the two k-side targets 4 (N_Z + N_G), and the scalar work of z, s(z),
+    the kernels, two exponentials and one logarithm; rows = N_Z + 1."""
+    nz, ng = cfg["n_z"], cfg["n_g"]
+    pts = (cfg["n_rad"] + cfg["n_ir"]) * cfg["n_ang"] * (nz + 1)
+    return pts * (2 * max(nz, ng) + 4 * (nz + ng) + GLUON_SCALAR_FLOPS)
+
+
+def ghost_point_flops(cfg: dict) -> float:
+    nz, ng = cfg["n_z"], cfg["n_g"]
+    pts = (cfg["n_rad"] + cfg["n_ir"]) * cfg["n_ang"] * (ng + 1)
+    return pts * (6 * nz + GHOST_SCALAR_FLOPS)
+
+
+def cpu_baseline(cfg: dict, c) -> dict:
+    """The oracle (plain FP64 C, OpenMP over rows) doing one step on the host."""
+    import numpy as np
+    import oracle
+    p = oracle.params(**cfg)
+    c = np.asarray(c, dtype=np.float64)
+    n = p.n_z + p.n_g
+    t0 = time.perf_counter()
+    J, F = oracle.jacobian(p, c, with_F=True)
+    d = oracle.lu_solve(J, F)
+    oracle.residual(p, c - d)
+    dt = time.perf_counter() - t0
+    return {"value": n * n / dt, "unit": "Jacobian entries/s", "cores": oracle.get_threads(),
+            "kind": "oracle", "seconds": dt,
+            "sample": "one full Newton iteration (J and F, LU solve, trial residual) of the "
+                      "N=64 workload, timed once with all host threads"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--solves", type=int, default=5, help="Newton solves timed for s/solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X and has no "
+              "multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads
+    from paper_1206_1779_amd import dse
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    name = "cfg2"
+    cfg = workloads.config(name)
+    s = dse.Solver(device="cuda:0", **cfg)
+    n = s.n
+    c = s.start_guess()
+
+    def step(cv):
+        J, F = s.jacobian(cv)
+        d = s.lu_solve(J, F)
+        return s.residual(cv - d)
+
+    for _ in range(args.warmup):
+        step(c)
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(c)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages, cnt = s.read_timings()
+    s.set_timing(False)
+    ms_step = dt / args.steps * 1e3
+    value = n * n / (dt / args.steps)
+
+    # Jacobian assembly alone (device time of its five stages)
+    t_asm = sum(stages) * 1e-3
+    # dominant kernel: the gluon point kernel, Jacobian mode
+    t_gl = stages[1] * 1e-3
+    a_gl = gluon_point_flops(cfg)
+    achieved = a_gl / t_gl / 1e12
+    roof = {"bound": "alu", "kernel": "point_kernel<gluon, 64, jacobian>",
+            "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+            "flops_per_launch": a_gl, "avg_launch_ms": t_gl * 1e3, "launches": cnt,
+            "ghost_kernel_ms": stages[2], "ghost_kernel_tflops": ghost_point_flops(cfg) / (stages[2] * 1e-3) / 1e12}
+
+    # s / Newton solve from the start guess to scaled residual < 1e-10
+    times, iters = [], []
+    for _ in range(args.solves):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = s.newton(tol=1e-10)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        iters.append(r.iters)
+
+    out = {
+        "metric": "Jacobian entries/s + s/Newton-solve at N=64; batched & adjoint vs plain",
+        "value": value, "unit": "Jacobian entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": workloads.WORKLOAD_NAMES[name], "n_z": cfg["n_z"], "n_g": cfg["n_g"],
+                   "n_rad": cfg["n_rad"], "n_ir": cfg["n_ir"], "n_ang": cfg["n_ang"],
+                   "g0": 1.0 / cfg["g0_inv"], "step": "J+F assembly, LU solve, trial residual"},
+        "assembly_entries_per_s": n * n / t_asm,
+        "assembly_ms": t_asm * 1e3,
+        "stage_ms": dict(zip(["dressing", "gluon_points", "ghost_points", "contract", "assemble"], stages)),
+        "newton_solve_s": statistics.median(times), "newton_iters": iters[0],
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        cb = cpu_baseline(cfg, c.cpu().numpy())
+        cb["gpu_speedup"] = value / cb["value"]
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

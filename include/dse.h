@@ -1,0 +1,187 @@
+/*
+ * dse.h -- C ABI of the MI355X (gfx950) ghost-gluon Dyson-Schwinger solver.
+ *
+ * Method: Hopfer, Alkofer, Haase, "Solving the Ghost-Gluon System of
+ * Yang-Mills Theory on GPUs" (arXiv:1206.1779).  The Landau-gauge ghost and
+ * gluon dressing functions G(p^2), Z(p^2) are expanded as
+ *     ln Z(x) = a_0/2 + sum_{j>=1} a_j T_j(s(x)),  ln G(x) = b_0/2 + ...
+ * with the mapping s(x) = log10(x/(Lambda eps)) / log10(Lambda/eps) (Sec. 3),
+ * and the renormalised DSEs (Sec. 3, MOM subtraction at x_Z = Lambda^2 for the
+ * gluon and x_G = 0 for the ghost)
+ *     z(x_i) = Z(x_i)^{-1} - Z(x_Z)^{-1} - Pi_Z(x_i) + Pi_Z(x_Z) = 0
+ *     g(x_i) = G(x_i)^{-1} - G(x_G)^{-1} - Pi_G(x_i) + Pi_G(x_G) = 0
+ * are collocated at the mapped Chebyshev roots and solved by Newton-Raphson
+ * with under-relaxation (Sec. 3).  Pi_Z and Pi_G are the radial x angular
+ * integrals of Sec. 2 (ghost loop with the (1-xi^2)^{3/2} angular weight,
+ * gluon loop with the kernels M, Q and the vertex dressing
+ * (G(y)G(z))^{-2-6 delta} (Z(y)Z(z))^{-3 delta}).
+ *
+ * Layouts (all FP64, row-major, device memory):
+ *   c  [n]      unknowns [a_0..a_{n_z-1}, b_0..b_{n_g-1}],  n = n_z + n_g
+ *   F  [n]      residual [z(x^Z_0..x^Z_{n_z-1}), g(x^G_0..x^G_{n_g-1})]
+ *   J  [n x n]  J[r*n + k] = dF_r / dc_k  (the Newton matrix of Sec. 3)
+ *
+ * Ownership: the caller allocates every device buffer, including one
+ * workspace of dse_workspace_bytes() bytes that stays alive (and untouched by
+ * the caller) until dse_destroy().  The library allocates no device memory.
+ * A context belongs to one HIP stream and one device and is not thread-safe.
+ *
+ * Synchrony: dse_residual, dse_jacobian and dse_start_guess enqueue work on
+ * the context's stream and return without synchronising.  dse_newton_solve
+ * synchronises (it reads the residual norm every iteration) and returns when
+ * the solve is finished.
+ *
+ * Errors: every call returns a dse_status and never throws.  Invalid
+ * arguments are reported before any launch (DSE_E_INVALID, message in
+ * dse_last_error).  HIP runtime failures give DSE_E_DEVICE.
+ */
+#ifndef DSE_H
+#define DSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSE_ABI_VERSION 1
+/* largest Chebyshev order per function */
+#define DSE_MAX_N 128
+
+typedef enum {
+  DSE_OK = 0,
+  DSE_E_INVALID = 1,   /* bad argument or parameter; nothing was launched      */
+  DSE_E_DEVICE = 2,    /* HIP runtime error                                    */
+  DSE_E_NOMEM = 3,     /* workspace smaller than dse_workspace_bytes()        */
+  DSE_E_SINGULAR = 4,  /* zero (or non-finite) pivot in the Newton LU          */
+  DSE_E_NOCONV = 5,    /* Newton did not converge within max_iter             */
+  DSE_E_NONFINITE = 6  /* residual or Jacobian not finite                      */
+} dse_status;
+
+typedef enum { DSE_FP64 = 0, DSE_MIXED = 1 } dse_precision;
+
+typedef struct dse_ctx dse_ctx; /* opaque */
+
+/* Problem definition (Sec. 2-3).  dse_params_default() fills the paper's
+ * physics: alpha(mu^2) = 1, N_c = 3, kappa = (93 - sqrt(1201))/98,
+ * delta = -9/44, gamma = -13/22. */
+typedef struct {
+  int32_t abi_version;   /* DSE_ABI_VERSION                                      */
+  int32_t n_z, n_g;      /* Chebyshev coefficients of ln Z (a) and ln G (b),
+                            1 .. DSE_MAX_N each                                  */
+  int32_t n_rad;         /* Gauss-Legendre nodes in ln y on [eps2, lambda2]     */
+  int32_t n_ir;          /* Gauss-Legendre nodes in ln y on the IR panel
+                            [eps2 exp(-ir_efolds), eps2] (stands for the
+                            integral from 0 to eps2 of the radial split, Sec. 3) */
+  int32_t n_ang;         /* Gauss-Legendre nodes in theta on (0, pi)            */
+  int32_t precision;     /* dse_precision                                        */
+  int32_t reserved_;
+  double eps2, lambda2;  /* interval [epsilon^2, Lambda^2] of the expansion      */
+  double ir_efolds;      /* length of the IR panel in ln y                       */
+  double alpha_mu;       /* alpha(mu^2) = g^2/(4 pi)                              */
+  double n_c;            /* number of colours                                    */
+  double g0_inv;         /* G(x_G = 0)^{-1}; 0 selects the scaling solution      */
+  double z_lambda_inv;   /* Z(x_Z = Lambda^2)^{-1}                               */
+  double kappa;          /* IR exponent (Z ~ x^{2 kappa}, G ~ x^{-kappa})        */
+  double delta, gamma;   /* ghost and gluon anomalous dimensions                 */
+} dse_params;
+
+/* Newton options (Sec. 3 under-relaxed Newton-Raphson).  The relaxation rho
+ * starts at 1 and is halved, at most max_halvings times, while the scaled
+ * residual of the trial point is not below the current one.  Convergence:
+ * scaled residual max_r |F_r| / S_r < tol, where S_r is the magnitude of the
+ * terms that cancel in F_r (direct term, parameter, and the sums of
+ * |integrand| at x_r and at the subtraction point).  Then extra_iters full
+ * steps follow, stopping early once rho ||Delta||_inf < step_tol. */
+typedef struct {
+  double tol;
+  int32_t max_iter;
+  int32_t extra_iters;
+  int32_t max_halvings;
+  int32_t reserved_;
+  double step_tol;
+} dse_newton_opts;
+
+typedef struct {
+  int32_t iters;           /* Newton iterations taken                             */
+  int32_t status;          /* dse_status of the solve                             */
+  double fnorm;            /* final scaled residual                               */
+  double fnorm2;           /* final ||F||_2                                       */
+  double fnorm_hist[128];  /* scaled residual before iteration i (i <= iters)     */
+  double relax_hist[128];  /* rho used in iteration i                             */
+  int32_t n_jacobians;     /* assemblies of J and F                               */
+  int32_t n_residuals;     /* residual-only evaluations (line search)             */
+  double t_total_ms;       /* wall time of the call                               */
+} dse_newton_report;
+
+/* Fills *p with the physics defaults above and the small grid
+ * n_z = n_g = 16, n_rad = 64, n_ir = 16, n_ang = 16, eps2 = 1e-6,
+ * lambda2 = 1e6, ir_efolds = 40, g0_inv = 0, z_lambda_inv = 1. */
+dse_status dse_params_default(dse_params* p);
+
+/* Device workspace bytes a context with these parameters needs (0 if the
+ * parameters are invalid). */
+size_t dse_workspace_bytes(const dse_params* p);
+
+/* Validates p, builds the quadrature grid, collocation points and Chebyshev
+ * tables on the host (Sec. 3 expansion and mapping; Sec. 2 radial and angular
+ * integrals) and uploads them into the workspace on `hip_stream` (a
+ * hipStream_t; NULL = default stream) of the current device.  d_workspace must
+ * be 256-byte aligned.  *out receives a host-allocated context. */
+dse_status dse_init(const dse_params* p, void* d_workspace, size_t ws_bytes,
+                    void* hip_stream, dse_ctx** out);
+
+/* Releases the host context (not the workspace).  NULL is allowed. */
+dse_status dse_destroy(dse_ctx* ctx);
+
+/* Writes the start guess to d_c[n]: the asymptotic forms of Sec. 2 (IR power
+ * laws joined to the one-loop UV logarithms, scale fixed by Z(Lambda^2))
+ * interpolated at the collocation points. */
+dse_status dse_start_guess(dse_ctx* ctx, double* d_c);
+
+/* Residual F(c) (Sec. 3, the collocated equations z(x_i), g(x_i)).
+ * d_S (nullable) receives the per-row scale S_r defined at dse_newton_opts. */
+dse_status dse_residual(dse_ctx* ctx, const double* d_c, double* d_F, double* d_S);
+
+/* Newton matrix J = dF/dc (Sec. 3 matrix layout, analytic derivatives of the
+ * integrands) and, if d_F != NULL, F at the same c. */
+dse_status dse_jacobian(dse_ctx* ctx, const double* d_c, double* d_J, double* d_F);
+
+/* Solves F(c) = 0 by the under-relaxed Newton iteration of Sec. 3 starting
+ * from d_c (overwritten by the last iterate).  opts may be NULL (tol 1e-10,
+ * max_iter 60, extra_iters 0, max_halvings 30, step_tol 1e-14); h_report
+ * (host memory) may be NULL.  Each step solves J Delta = F with an FP64 LU
+ * with partial pivoting on the device.  Returns DSE_E_NOCONV with the last
+ * iterate in d_c if max_iter is reached. */
+dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* opts,
+                            dse_newton_report* h_report);
+
+/* Solves J x = b (trans = 0) or J^T x = b (trans != 0) for a row-major
+ * n x n d_J with the device LU (partial pivoting).  d_J is not modified; the
+ * factors go to the workspace.  d_x may equal d_b. */
+dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, double* d_x,
+                        int32_t trans);
+
+const char* dse_status_string(dse_status s);
+/* Message of the last failed call on ctx (or of the last failed dse_init when
+ * ctx is NULL). */
+const char* dse_last_error(const dse_ctx* ctx);
+
+/* Numbers that size the problem: n = n_z + n_g, radial nodes, angular nodes. */
+dse_status dse_sizes(const dse_ctx* ctx, int32_t* n, int32_t* n_radial, int32_t* n_angular);
+
+/* Device-time instrumentation of dse_jacobian, for benchmarks.  While on,
+ * every dse_jacobian call records HIP events on the context's stream around
+ * its stages (no synchronisation at record time).  dse_read_timings()
+ * synchronises, and returns the average milliseconds per call since timing
+ * was switched on: [0] dressing, [1] gluon point kernel, [2] ghost point
+ * kernel, [3] B.T contraction, [4] assembly; *count = calls averaged.
+ * dse_set_timing() resets the averages. */
+dse_status dse_set_timing(dse_ctx* ctx, int32_t on);
+dse_status dse_read_timings(dse_ctx* ctx, double* ms5, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -94,6 +94,7 @@ def load():
             "dse_ref_start_guess": (C.c_int, [P, _D]),
             "dse_ref_newton": (C.c_int, [P, _D, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
             "dse_ref_set_order": (None, [C.c_int]),
+            "dse_ref_set_jitter": (None, [C.c_double]),
             "dse_ref_set_threads": (None, [C.c_int]),
             "dse_ref_get_threads": (C.c_int, []),
         }
@@ -316,6 +317,10 @@ def newton(p: Params, c0=None, tol=1e-10, max_iter=60, extra_iters=2, max_halvin
 
 def set_order(reversed_: bool):
     load().dse_ref_set_order(1 if reversed_ else 0)
+
+
+def set_jitter(rel: float):
+    load().dse_ref_set_jitter(float(rel))
 
 
 def set_threads(n: int):

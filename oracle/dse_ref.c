@@ -38,8 +38,10 @@
 
 static int g_reversed = 0;
 static int g_threads = 0;
+static double g_jitter = 0.0;
 
 void dse_ref_set_order(int reversed) { g_reversed = reversed ? 1 : 0; }
+void dse_ref_set_jitter(double rel) { g_jitter = rel; }
 void dse_ref_set_threads(int n) { g_threads = n > 0 ? n : 0; }
 int dse_ref_get_threads(void) {
 #ifdef _OPENMP
@@ -279,6 +281,11 @@ int dse_ref_grid(const dse_ref_params* p, double* y, double* W, double* theta, d
   for (int k = 0; k < p->n_ang; ++k) {
     theta[k] = 0.5 * REF_PI * (1.0 + u[k]);
     v[k] = 0.5 * REF_PI * wu[k];
+  }
+  /* rounding-floor probe: scale every weight by 1 +- g_jitter (0 by default) */
+  if (g_jitter != 0.0) {
+    for (int i = 0; i < p->n_ir + p->n_rad; ++i) W[i] *= 1.0 + ((i * 7919 % 13) % 2 ? g_jitter : -g_jitter);
+    for (int k = 0; k < p->n_ang; ++k) v[k] *= 1.0 + ((k * 104729 % 11) % 2 ? g_jitter : -g_jitter);
   }
   consts kc = make_consts(p);
   for (int i = 0; i < p->n_z; ++i)

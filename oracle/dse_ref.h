@@ -142,6 +142,10 @@ int dse_ref_newton(const dse_ref_params* p, double* c, const dse_ref_newton_opts
 /* Summation order of all quadrature sums: 0 forward, 1 reversed (used to
  * measure the oracle's own rounding floor). */
 void dse_ref_set_order(int reversed);
+/* Multiplies every quadrature weight by 1 +- rel (fixed sign pattern) to probe
+ * how far the solution moves under rounding-level changes of the discrete
+ * problem; 0 (default) switches it off. */
+void dse_ref_set_jitter(double rel);
 /* Number of OpenMP threads used (0 = library default). */
 void dse_ref_set_threads(int n);
 int dse_ref_get_threads(void);

@@ -1,0 +1,653 @@
+// dse_host.hip -- host side of the C ABI: parameter checks, quadrature grid
+// and Chebyshev tables, workspace layout, the Newton driver.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "dse_impl.h"
+
+struct dse_ctx {
+  dse_params p;
+  dse::Views v;
+  dse::Phys ph;
+  hipStream_t st;
+  int device;
+  char* ws;
+  size_t ws_bytes;
+  bool timing;
+  // event ring: per timed dse_jacobian, events before dressing, before the
+  // gluon point kernel, between gluon and ghost, after ghost, after the
+  // contraction, after the assembly
+  static constexpr int kRing = 64;
+  static constexpr int kEv = 6;
+  hipEvent_t ev[kRing][kEv];
+  int ring_count;
+  double acc_ms[5];
+  int acc_n;
+  char err[512];
+};
+
+static char g_init_err[512];
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+void set_err(char* buf, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, 512, fmt, ap);
+  va_end(ap);
+}
+
+#define HIP_TRY(ctx, expr)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      set_err((ctx)->err, "%s: %s", #expr, hipGetErrorString(e_));                  \
+      return DSE_E_DEVICE;                                                          \
+    }                                                                               \
+  } while (0)
+
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1]: Newton's method on
+// the Legendre polynomial evaluated by Bonnet's recursion, started from the
+// Tricomi estimate of the k-th root.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int k = 1; k <= (n + 1) / 2; ++k) {
+    const double th = kPi * (4.0 * k - 1.0) / (4.0 * n + 2.0);
+    double r = (1.0 - (n - 1.0) / (8.0 * n * n * n)) * cos(th);
+    double dP = 1.0;
+    for (int it = 0; it < 64; ++it) {
+      double P0 = 1.0, P1 = r;
+      for (int m = 2; m <= n; ++m) {
+        const double P2 = ((2.0 * m - 1.0) * r * P1 - (m - 1.0) * P0) / m;
+        P0 = P1;
+        P1 = P2;
+      }
+      if (n == 1) { P1 = r; P0 = 1.0; }
+      dP = n * (P0 - r * P1) / (1.0 - r * r);
+      const double step = P1 / dP;
+      r -= step;
+      if (fabs(step) <= 1e-16 * fabs(r) + 1e-300) {
+        P0 = 1.0; P1 = r;
+        for (int m = 2; m <= n; ++m) {
+          const double P2 = ((2.0 * m - 1.0) * r * P1 - (m - 1.0) * P0) / m;
+          P0 = P1;
+          P1 = P2;
+        }
+        if (n == 1) { P1 = r; P0 = 1.0; }
+        dP = n * (P0 - r * P1) / (1.0 - r * r);
+        break;
+      }
+    }
+    const double wt = 2.0 / ((1.0 - r * r) * dP * dP);
+    x[n - k] = r;
+    w[n - k] = wt;
+    x[k - 1] = -r;
+    w[k - 1] = wt;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+// Tilde-T_j(s) for j < m with Tilde-T_0 = 1/2 (the c_0/2 convention, Sec. 3).
+void cheb_row(double s, int m, double* out) {
+  double a = 1.0, b = s;
+  for (int j = 0; j < m; ++j) {
+    out[j] = j == 0 ? 0.5 : (j == 1 ? s : 0.0);
+    if (j >= 2) {
+      const double c = 2.0 * s * b - a;
+      out[j] = c;
+      a = b;
+      b = c;
+    }
+  }
+}
+
+dse_status validate(const dse_params* p, char* err) {
+  if (!p) { set_err(err, "params is NULL"); return DSE_E_INVALID; }
+  if (p->abi_version != DSE_ABI_VERSION) {
+    set_err(err, "abi_version %d, library has %d", p->abi_version, DSE_ABI_VERSION);
+    return DSE_E_INVALID;
+  }
+  if (p->n_z < 1 || p->n_z > DSE_MAX_N || p->n_g < 1 || p->n_g > DSE_MAX_N) {
+    set_err(err, "n_z = %d, n_g = %d: each must be in [1, %d]", p->n_z, p->n_g, DSE_MAX_N);
+    return DSE_E_INVALID;
+  }
+  if (p->n_rad < 1 || p->n_rad > 65536 || p->n_ir < 0 || p->n_ir > 65536 || p->n_ang < 1 ||
+      p->n_ang > 65536) {
+    set_err(err, "quadrature sizes n_rad = %d, n_ir = %d, n_ang = %d out of range", p->n_rad, p->n_ir,
+            p->n_ang);
+    return DSE_E_INVALID;
+  }
+  const double vals[] = {p->eps2, p->lambda2, p->ir_efolds, p->alpha_mu, p->n_c, p->g0_inv,
+                         p->z_lambda_inv, p->kappa, p->delta, p->gamma};
+  for (double d : vals)
+    if (!isfinite(d)) { set_err(err, "non-finite parameter"); return DSE_E_INVALID; }
+  if (!(p->eps2 > 0.0) || !(p->lambda2 > p->eps2)) {
+    set_err(err, "need 0 < eps2 < lambda2 (got %g, %g)", p->eps2, p->lambda2);
+    return DSE_E_INVALID;
+  }
+  if (!(p->alpha_mu > 0.0) || !(p->n_c > 0.0)) {
+    set_err(err, "alpha_mu and n_c must be positive");
+    return DSE_E_INVALID;
+  }
+  if (p->n_ir > 0 && !(p->ir_efolds > 0.0)) {
+    set_err(err, "ir_efolds must be positive when n_ir > 0");
+    return DSE_E_INVALID;
+  }
+  if (p->g0_inv < 0.0 || !(p->z_lambda_inv > 0.0)) {
+    set_err(err, "need g0_inv >= 0 and z_lambda_inv > 0");
+    return DSE_E_INVALID;
+  }
+  if (p->precision != DSE_FP64 && p->precision != DSE_MIXED) {
+    set_err(err, "precision %d unknown", p->precision);
+    return DSE_E_INVALID;
+  }
+  return DSE_OK;
+}
+
+dse::Phys make_phys(const dse_params& p) {
+  dse::Phys ph;
+  ph.C = p.alpha_mu * p.n_c / (2.0 * kPi * kPi);
+  ph.omega = 11.0 * p.n_c * p.alpha_mu / (12.0 * kPi);
+  ph.e1 = -2.0 - 6.0 * p.delta;
+  ph.e2 = -3.0 * p.delta;
+  ph.ln_eps2 = log(p.eps2);
+  ph.ln_lam2 = log(p.lambda2);
+  ph.L0 = 0.5 * (ph.ln_eps2 + ph.ln_lam2);
+  ph.invL1 = 1.0 / (0.5 * (ph.ln_lam2 - ph.ln_eps2));
+  ph.kappa = p.kappa;
+  ph.delta = p.delta;
+  ph.gamma = p.gamma;
+  ph.g0_inv = p.g0_inv;
+  ph.z_lambda_inv = p.z_lambda_inv;
+  return ph;
+}
+
+}  // namespace
+
+namespace dse {
+
+// Carves the workspace; with base == nullptr only sizes it.
+size_t layout(const dse_params& p, Views* v, char* base) {
+  Views t{};
+  t.n_z = p.n_z;
+  t.n_g = p.n_g;
+  t.n = p.n_z + p.n_g;
+  t.NJ = padded_order(p.n_z > p.n_g ? p.n_z : p.n_g);
+  t.Q = p.n_rad + p.n_ir;
+  t.Qp = pad_up(t.Q, kQPad);
+  t.K = p.n_ang;
+  t.Kp = pad_up(t.K, kKPad);
+  t.RZ = p.n_z + 1;
+  t.RG = p.n_g + 1;
+  t.nqt = t.Qp / 64;
+  t.Rb = 2 * t.RZ + t.RG;
+  t.Rbp = pad_up(t.Rb, 16);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* ptr = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return ptr;
+  };
+  const size_t d = sizeof(double);
+  t.coef = (double*)take(2 * t.NJ * d);
+  t.y = (double*)take(t.Qp * d);
+  t.W = (double*)take(t.Qp * d);
+  t.lnZy = (double*)take(t.Qp * d);
+  t.lnGy = (double*)take(t.Qp * d);
+  t.Ttab = (double*)take((size_t)t.Qp * t.NJ * d);
+  t.Text = (double*)take((size_t)t.n * t.NJ * d);
+  t.xrow = (double*)take((t.RZ + t.RG) * d);
+  t.lnX = (double*)take(t.n * d);
+  t.ang = (double*)take(5 * t.Kp * d);
+  t.Bm = (double*)take((size_t)t.Rbp * t.Qp * d);
+  t.Dp = (double*)take((size_t)(2 * t.RZ + t.RG) * t.nqt * t.NJ * d);
+  t.Pip = (double*)take((size_t)2 * (t.RZ + t.RG) * t.nqt * d);
+  t.Absp = (double*)take((size_t)(t.RZ + t.RG) * t.nqt * d);
+  t.Eq = (double*)take((size_t)t.Rbp * t.NJ * d);
+  t.LU = (double*)take((size_t)t.n * t.n * d);
+  t.piv = (int32_t*)take(t.n * sizeof(int32_t));
+  t.flag = (int32_t*)take(4 * sizeof(int32_t));
+  t.F = (double*)take(t.n * d);
+  t.S = (double*)take(t.n * d);
+  t.Ft = (double*)take(t.n * d);
+  t.St = (double*)take(t.n * d);
+  t.dlt = (double*)take(t.n * d);
+  t.ct = (double*)take(t.n * d);
+  t.J = (double*)take((size_t)t.n * t.n * d);
+  t.scal = (double*)take(8 * d);
+  if (v) *v = t;
+  return off;
+}
+
+}  // namespace dse
+
+namespace {
+
+// Host tables, uploaded once.
+dse_status build_tables(dse_ctx* ctx) {
+  const dse_params& p = ctx->p;
+  const dse::Views& v = ctx->v;
+  const dse::Phys& ph = ctx->ph;
+  const int NJ = v.NJ;
+  std::vector<double> y(v.Qp, 1.0), W(v.Qp, 0.0), sq(v.Qp, 0.0);
+  std::vector<double> u, wu;
+  int q = 0;
+  if (p.n_ir > 0) {
+    gauss_legendre(p.n_ir, u, wu);
+    const double a = ph.ln_eps2 - p.ir_efolds, b = ph.ln_eps2;
+    for (int i = 0; i < p.n_ir; ++i, ++q) {
+      const double tq = 0.5 * (a + b) + 0.5 * (b - a) * u[i];
+      y[q] = exp(tq);
+      W[q] = 0.5 * (b - a) * wu[i] * y[q];
+      sq[q] = -1.0;  // below eps2 the series is frozen at s = -1
+    }
+  }
+  gauss_legendre(p.n_rad, u, wu);
+  const double L1 = 0.5 * (ph.ln_lam2 - ph.ln_eps2);
+  for (int i = 0; i < p.n_rad; ++i, ++q) {
+    const double tq = ph.L0 + L1 * u[i];
+    y[q] = exp(tq);
+    W[q] = L1 * wu[i] * y[q];
+    sq[q] = u[i];  // the mapped coordinate of a main-panel node is the GL node
+  }
+  std::vector<double> Ttab((size_t)v.Qp * NJ);
+  for (int i = 0; i < v.Qp; ++i) cheb_row(sq[i], NJ, &Ttab[(size_t)i * NJ]);
+
+  std::vector<double> Text((size_t)v.n * NJ), xrow(v.RZ + v.RG);
+  for (int r = 0; r < v.n; ++r) {
+    const bool gl = r < p.n_z;
+    const int N = gl ? p.n_z : p.n_g;
+    const int i = gl ? r : r - p.n_z;
+    const double s = -cos(kPi * (i + 0.5) / N);
+    cheb_row(s, NJ, &Text[(size_t)r * NJ]);
+    const double x = exp(ph.L0 + L1 * s);
+    xrow[gl ? i : v.RZ + i] = x;
+  }
+  xrow[v.RZ - 1] = p.lambda2;         // gluon subtraction point x_Z = Lambda^2
+  xrow[v.RZ + v.RG - 1] = 0.0;        // ghost subtraction point x_G = 0
+
+  std::vector<double> ang(5 * (size_t)v.Kp, 0.0);
+  gauss_legendre(p.n_ang, u, wu);
+  for (int k = 0; k < v.Kp; ++k) {
+    if (k < p.n_ang) {
+      const double th = 0.5 * kPi * (1.0 + u[k]);
+      const double vk = 0.5 * kPi * wu[k];
+      const double sn = sin(th), sh = sin(0.5 * th);
+      ang[k] = cos(th);
+      ang[v.Kp + k] = sh * sh;
+      ang[2 * v.Kp + k] = vk * sn * sn;
+      ang[3 * v.Kp + k] = vk * sn * sn * sn * sn;
+      ang[4 * v.Kp + k] = sn * sn;
+    } else {
+      ang[v.Kp + k] = 0.5;  // padding angle: zero weight
+    }
+  }
+  std::vector<double> zeros((size_t)v.Rbp * v.Qp, 0.0);
+  hipStream_t st = ctx->st;
+  HIP_TRY(ctx, hipMemcpyAsync(v.y, y.data(), v.Qp * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(v.W, W.data(), v.Qp * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(v.Ttab, Ttab.data(), Ttab.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(v.Text, Text.data(), Text.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(v.xrow, xrow.data(), xrow.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(v.ang, ang.data(), ang.size() * 8, hipMemcpyHostToDevice, st));
+  // the padding rows of B must be finite (they only feed padding rows of Eq)
+  HIP_TRY(ctx, hipMemcpyAsync(v.Bm, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  return DSE_OK;
+}
+
+dse_status check_ctx(const dse_ctx* ctx) { return ctx ? DSE_OK : DSE_E_INVALID; }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+dse_status eval_residual(dse_ctx* ctx, const double* c, double* F, double* S) {
+  const dse::Views& v = ctx->v;
+  HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, c, ctx->st));
+  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, false, ctx->st, nullptr));
+  HIP_TRY(ctx, dse::launch_residual_rows(v, ctx->ph, F, S, ctx->st));
+  return DSE_OK;
+}
+
+dse_status flush_timings(dse_ctx* ctx);
+
+dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, double* S) {
+  const dse::Views& v = ctx->v;
+  hipEvent_t* ev = nullptr;
+  if (ctx->timing) {
+    if (ctx->ring_count == dse_ctx::kRing) {
+      dse_status s = flush_timings(ctx);
+      if (s != DSE_OK) return s;
+    }
+    ev = ctx->ev[ctx->ring_count++];
+  }
+  if (ev) HIP_TRY(ctx, hipEventRecord(ev[0], ctx->st));
+  HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, c, ctx->st));
+  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, true, ctx->st, ev ? ev + 1 : nullptr));
+  HIP_TRY(ctx, dse::launch_contract(v, ctx->st));
+  if (ev) HIP_TRY(ctx, hipEventRecord(ev[4], ctx->st));
+  HIP_TRY(ctx, dse::launch_assemble(v, ctx->ph, J, F, S, ctx->st));
+  if (ev) HIP_TRY(ctx, hipEventRecord(ev[5], ctx->st));
+  return DSE_OK;
+}
+
+// Folds the recorded event pairs into the running sums (synchronises).
+dse_status flush_timings(dse_ctx* ctx) {
+  for (int i = 0; i < ctx->ring_count; ++i) {
+    hipEvent_t* e = ctx->ev[i];
+    HIP_TRY(ctx, hipEventSynchronize(e[5]));
+    float ms[5];
+    for (int k = 0; k < 5; ++k) HIP_TRY(ctx, hipEventElapsedTime(&ms[k], e[k], e[k + 1]));
+    for (int k = 0; k < 5; ++k) ctx->acc_ms[k] += ms[k];
+    ++ctx->acc_n;
+  }
+  ctx->ring_count = 0;
+  return DSE_OK;
+}
+
+// Reads merit, ||F||_2, ||d||_inf and the LU flag (synchronises the stream).
+dse_status read_norms(dse_ctx* ctx, const double* F, const double* S, const double* d, double out[3]) {
+  HIP_TRY(ctx, dse::launch_norms(ctx->v, F, S, d, ctx->v.scal, ctx->st));
+  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->v.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
+  return DSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dse_status_string(dse_status s) {
+  switch (s) {
+    case DSE_OK: return "ok";
+    case DSE_E_INVALID: return "invalid argument";
+    case DSE_E_DEVICE: return "HIP device error";
+    case DSE_E_NOMEM: return "workspace too small";
+    case DSE_E_SINGULAR: return "singular Newton matrix";
+    case DSE_E_NOCONV: return "Newton iteration did not converge";
+    case DSE_E_NONFINITE: return "non-finite residual or Jacobian";
+  }
+  return "unknown status";
+}
+
+const char* dse_last_error(const dse_ctx* ctx) { return ctx ? ctx->err : g_init_err; }
+
+dse_status dse_params_default(dse_params* p) {
+  if (!p) return DSE_E_INVALID;
+  memset(p, 0, sizeof(*p));
+  p->abi_version = DSE_ABI_VERSION;
+  p->n_z = p->n_g = 16;
+  p->n_rad = 64;
+  p->n_ir = 16;
+  p->n_ang = 16;
+  p->precision = DSE_FP64;
+  p->eps2 = 1e-6;
+  p->lambda2 = 1e6;
+  p->ir_efolds = 40.0;
+  p->alpha_mu = 1.0;
+  p->n_c = 3.0;
+  p->g0_inv = 0.0;
+  p->z_lambda_inv = 1.0;
+  p->kappa = (93.0 - sqrt(1201.0)) / 98.0;
+  p->delta = -9.0 / 44.0;
+  p->gamma = -13.0 / 22.0;
+  return DSE_OK;
+}
+
+size_t dse_workspace_bytes(const dse_params* p) {
+  char tmp[512];
+  if (validate(p, tmp) != DSE_OK) return 0;
+  return dse::layout(*p, nullptr, nullptr);
+}
+
+dse_status dse_init(const dse_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                    dse_ctx** out) {
+  if (!out) { set_err(g_init_err, "out is NULL"); return DSE_E_INVALID; }
+  *out = nullptr;
+  dse_status s = validate(p, g_init_err);
+  if (s != DSE_OK) return s;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255u)) {
+    set_err(g_init_err, "workspace must be a non-NULL, 256-byte aligned device pointer");
+    return DSE_E_INVALID;
+  }
+  const size_t need = dse::layout(*p, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_err(g_init_err, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return DSE_E_NOMEM;
+  }
+  dse_ctx* ctx = new (std::nothrow) dse_ctx();
+  if (!ctx) { set_err(g_init_err, "host allocation failed"); return DSE_E_INVALID; }
+  ctx->p = *p;
+  ctx->ph = make_phys(*p);
+  ctx->st = (hipStream_t)hip_stream;
+  ctx->ws = (char*)d_workspace;
+  ctx->ws_bytes = ws_bytes;
+  dse::layout(*p, &ctx->v, ctx->ws);
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    set_err(g_init_err, "hipGetDevice failed");
+    delete ctx;
+    return DSE_E_DEVICE;
+  }
+  for (auto& row : ctx->ev)
+    for (auto& e : row) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        set_err(g_init_err, "hipEventCreate failed");
+        delete ctx;
+        return DSE_E_DEVICE;
+      }
+    }
+  s = build_tables(ctx);
+  if (s != DSE_OK) {
+    set_err(g_init_err, "%s", ctx->err);
+    for (auto& row : ctx->ev)
+      for (auto& e : row) (void)hipEventDestroy(e);
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return DSE_OK;
+}
+
+dse_status dse_destroy(dse_ctx* ctx) {
+  if (!ctx) return DSE_OK;
+  for (auto& row : ctx->ev)
+    for (auto& e : row) (void)hipEventDestroy(e);
+  delete ctx;
+  return DSE_OK;
+}
+
+dse_status dse_sizes(const dse_ctx* ctx, int32_t* n, int32_t* nr, int32_t* na) {
+  if (!ctx) return DSE_E_INVALID;
+  if (n) *n = ctx->v.n;
+  if (nr) *nr = ctx->v.Q;
+  if (na) *na = ctx->v.K;
+  return DSE_OK;
+}
+
+// Start guess of Sec. 2's asymptotic forms, as interpolation coefficients at
+// the collocation points:  L(x) = ln(1 + omega ln(1 + x / mu2)),
+//   ln G0 = -kappa ln((x + m2) / (x + mu2)) + delta L,
+//   ln Z0 = 2 kappa ln(x / (x + mu2)) + gamma L   (scaling, g0_inv = 0),
+//   ln Z0 = ln(x / (x + mu2)) + gamma L           (decoupling),
+// mu2 from Z0(Lambda^2) = 1/z_lambda_inv, m2 = mu2 g0_inv^{1/kappa}.
+dse_status dse_start_guess(dse_ctx* ctx, double* d_c) {
+  if (!ctx || !d_c) return DSE_E_INVALID;
+  DeviceGuard dg(ctx->device);
+  const dse_params& p = ctx->p;
+  const dse::Phys& ph = ctx->ph;
+  const double L1 = 0.5 * (ph.ln_lam2 - ph.ln_eps2);
+  const double zl = 1.0 / p.z_lambda_inv;
+  const double r = pow(zl, 1.0 / p.gamma);  // = 1 + omega ln(1 + Lambda^2/mu2)
+  const double mu2 = r > 1.0 + 1e-9 ? p.lambda2 / expm1((r - 1.0) / ph.omega) : 1e6 * p.lambda2;
+  const double m2 = p.g0_inv > 0.0 ? mu2 * pow(p.g0_inv, 1.0 / p.kappa) : 0.0;
+  std::vector<double> c(ctx->v.n, 0.0);
+  for (int f = 0; f < 2; ++f) {
+    const int N = f == 0 ? p.n_z : p.n_g;
+    double* o = c.data() + (f == 0 ? 0 : p.n_z);
+    for (int i = 0; i < N; ++i) {
+      const double phi = kPi * (i + 0.5) / N;
+      const double s = -cos(phi);
+      const double x = exp(ph.L0 + L1 * s);
+      const double L = log1p(ph.omega * log1p(x / mu2));
+      double val;
+      if (f == 0)
+        val = (p.g0_inv > 0.0 ? 1.0 : 2.0 * p.kappa) * log(x / (x + mu2)) + p.gamma * L;
+      else
+        val = -p.kappa * log((x + m2) / (x + mu2)) + p.delta * L;
+      // T_j(-cos phi) = cos(j (pi - phi)) = (-1)^j cos(j phi)
+      for (int j = 0; j < N; ++j) o[j] += (2.0 / N) * val * ((j & 1) ? -1.0 : 1.0) * cos(j * phi);
+    }
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(d_c, c.data(), c.size() * 8, hipMemcpyHostToDevice, ctx->st));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
+  return DSE_OK;
+}
+
+dse_status dse_residual(dse_ctx* ctx, const double* d_c, double* d_F, double* d_S) {
+  if (!ctx) return DSE_E_INVALID;
+  if (!d_c || !d_F) { set_err(ctx->err, "d_c and d_F must not be NULL"); return DSE_E_INVALID; }
+  DeviceGuard dg(ctx->device);
+  return eval_residual(ctx, d_c, d_F, d_S);
+}
+
+dse_status dse_jacobian(dse_ctx* ctx, const double* d_c, double* d_J, double* d_F) {
+  if (!ctx) return DSE_E_INVALID;
+  if (!d_c || !d_J) { set_err(ctx->err, "d_c and d_J must not be NULL"); return DSE_E_INVALID; }
+  DeviceGuard dg(ctx->device);
+  return eval_jacobian(ctx, d_c, d_J, d_F, d_F ? ctx->v.St : nullptr);
+}
+
+dse_status dse_set_timing(dse_ctx* ctx, int32_t on) {
+  if (!ctx) return DSE_E_INVALID;
+  DeviceGuard dg(ctx->device);
+  dse_status s = flush_timings(ctx);
+  ctx->timing = on != 0;
+  for (double& a : ctx->acc_ms) a = 0.0;
+  ctx->acc_n = 0;
+  return s;
+}
+
+dse_status dse_read_timings(dse_ctx* ctx, double* ms5, int32_t* count) {
+  if (!ctx || !ms5) return DSE_E_INVALID;
+  DeviceGuard dg(ctx->device);
+  dse_status s = flush_timings(ctx);
+  if (s != DSE_OK) return s;
+  for (int i = 0; i < 5; ++i) ms5[i] = ctx->acc_n ? ctx->acc_ms[i] / ctx->acc_n : 0.0;
+  if (count) *count = ctx->acc_n;
+  return DSE_OK;
+}
+
+dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, double* d_x, int32_t trans) {
+  if (!ctx) return DSE_E_INVALID;
+  if (!d_J || !d_b || !d_x) { set_err(ctx->err, "NULL argument"); return DSE_E_INVALID; }
+  DeviceGuard dg(ctx->device);
+  HIP_TRY(ctx, dse::launch_lu_solve(ctx->v, d_J, d_b, d_x, trans, ctx->st));
+  int32_t flag = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
+  if (flag == DSE_E_SINGULAR) { set_err(ctx->err, "zero pivot"); return DSE_E_SINGULAR; }
+  return DSE_OK;
+}
+
+dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* opts, dse_newton_report* rep) {
+  if (!ctx) return DSE_E_INVALID;
+  if (!d_c) { set_err(ctx->err, "d_c is NULL"); return DSE_E_INVALID; }
+  DeviceGuard dg(ctx->device);
+  const auto t0 = std::chrono::steady_clock::now();
+  dse_newton_opts o;
+  if (opts) {
+    o = *opts;
+  } else {
+    o.tol = 1e-10; o.max_iter = 60; o.extra_iters = 0; o.max_halvings = 30; o.reserved_ = 0; o.step_tol = 1e-14;
+  }
+  if (!(o.tol > 0.0) || o.max_iter < 0 || o.extra_iters < 0 || o.max_halvings < 0) {
+    set_err(ctx->err, "invalid Newton options");
+    return DSE_E_INVALID;
+  }
+  dse_newton_report r;
+  memset(&r, 0, sizeof(r));
+  const dse::Views& v = ctx->v;
+  const int n = v.n;
+  hipStream_t st = ctx->st;
+  double nrm[3];
+  dse_status s = eval_residual(ctx, d_c, v.F, v.S);
+  if (s == DSE_OK) s = read_norms(ctx, v.F, v.S, nullptr, nrm);
+  ++r.n_residuals;
+  double f = nrm[0];
+  r.fnorm_hist[0] = f;
+  int it = 0, extra = 0;
+  dse_status status = s;
+  if (s == DSE_OK && !isfinite(f)) status = DSE_E_NONFINITE;
+  while (status == DSE_OK) {
+    if (f < o.tol) {
+      if (extra >= o.extra_iters) break;
+      ++extra;
+    }
+    if (it >= o.max_iter) { status = DSE_E_NOCONV; break; }
+    // J and F at c (F is recomputed with J; it is the same evaluation)
+    if ((s = eval_jacobian(ctx, d_c, v.J, v.F, v.S)) != DSE_OK) { status = s; break; }
+    ++r.n_jacobians;
+    if (hipGetLastError() != hipSuccess) { status = DSE_E_DEVICE; break; }
+    HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, st));
+    const bool conv = f < o.tol;
+    double rho = 1.0, ft = INFINITY, dinf = 0.0;
+    for (int h = 0;; ++h) {
+      HIP_TRY(ctx, dse::launch_axpy(n, d_c, rho, v.dlt, v.ct, st));
+      if ((s = eval_residual(ctx, v.ct, v.Ft, v.St)) != DSE_OK) { status = s; break; }
+      ++r.n_residuals;
+      if ((s = read_norms(ctx, v.Ft, v.St, v.dlt, nrm)) != DSE_OK) { status = s; break; }
+      if (h == 0) {
+        int32_t flag = 0;
+        HIP_TRY(ctx, hipMemcpy(&flag, v.flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (flag == DSE_E_SINGULAR) { status = DSE_E_SINGULAR; set_err(ctx->err, "zero pivot"); break; }
+      }
+      ft = isfinite(nrm[0]) ? nrm[0] : INFINITY;
+      dinf = nrm[2];
+      if (conv || ft < f || h >= o.max_halvings) break;
+      rho *= 0.5;
+    }
+    if (status != DSE_OK) break;
+    if (!isfinite(ft)) { status = DSE_E_NONFINITE; break; }
+    HIP_TRY(ctx, hipMemcpyAsync(d_c, v.ct, n * 8, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(v.F, v.Ft, n * 8, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(v.S, v.St, n * 8, hipMemcpyDeviceToDevice, st));
+    f = ft;
+    ++it;
+    if (it < 128) { r.fnorm_hist[it] = f; r.relax_hist[it - 1] = rho; }
+    r.fnorm2 = nrm[1];
+    if (conv && rho * dinf < o.step_tol) break;
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  r.iters = it;
+  r.status = status;
+  r.fnorm = f;
+  if (it == 0) {
+    if (read_norms(ctx, v.F, v.S, nullptr, nrm) == DSE_OK) r.fnorm2 = nrm[1];
+  }
+  r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = r;
+  if (status == DSE_E_NOCONV) set_err(ctx->err, "no convergence after %d iterations (scaled residual %g)", it, f);
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// dse_impl.h -- internal declarations of the HIP implementation (not part of
+// the C ABI).  Shared by the host driver and the kernel translation unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dse.h"
+
+namespace dse {
+
+// Padding of the radial grid (multiple of every q-tile), of the angular grid
+// and of the Chebyshev order (the point kernels are instantiated per padded
+// order).
+constexpr int kQPad = 64;
+constexpr int kKPad = 8;
+
+inline int pad_up(int v, int m) { return (v + m - 1) / m * m; }
+// Padded Chebyshev order: 16, 32, 48, 64, 96 or 128.
+inline int padded_order(int n) {
+  if (n <= 16) return 16;
+  if (n <= 32) return 32;
+  if (n <= 48) return 48;
+  if (n <= 64) return 64;
+  if (n <= 96) return 96;
+  return 128;
+}
+
+// Derived physical constants handed to every kernel by value.
+struct Phys {
+  double C;          // alpha N_c / (2 pi^2)  (= g^2 N_c / (2 pi)^3)
+  double omega;      // 11 N_c alpha / (12 pi)
+  double e1, e2;     // -2 - 6 delta, -3 delta
+  double L0, invL1;  // s = (ln u - L0) / L1
+  double ln_eps2, ln_lam2;
+  double kappa, delta, gamma;
+  double g0_inv, z_lambda_inv;
+};
+
+// Device views into the caller's workspace.
+struct Views {
+  int n_z, n_g, n;       // orders and unknowns
+  int NJ;                // padded order
+  int Q, Qp, K, Kp;      // radial / angular nodes and their padded counts
+  int RZ, RG;            // gluon rows (n_z + subtraction at Lambda^2), ghost rows (n_g + x = 0)
+  int nqt;               // q-tiles per row used by the point kernels (Qp / 64 * 4 max)
+  int Rb, Rbp;           // rows of the B matrix (2 RZ + RG) and padded to 16
+  // tables
+  double* coef;          // [2][NJ] a then b, zero padded, j = 0 term halved
+  double* y;             // [Qp] radial nodes (padding: y = 1, W = 0)
+  double* W;             // [Qp] radial weights including the factor y
+  double* lnZy;          // [Qp] ln Z at the radial nodes
+  double* lnGy;          // [Qp]
+  double* Ttab;          // [Qp][NJ] Tilde-T_j(s(y_q))
+  double* Text;          // [n][NJ]  Tilde-T_j(s(x_r)) at the collocation points
+  double* xrow;          // [RZ + RG] external momentum of each row
+  double* lnX;           // [n] ln Z (gluon rows) / ln G (ghost rows) at x_r
+  double* ang;           // [5][Kp] cos, sin^2(theta/2), v sin^2, v sin^4, sin^2
+  // per assembly
+  double* Bm;            // [Rbp][Qp] angular sums: rows gluon-a | gluon-b | ghost-b
+  double* Dp;            // [3][RZ or RG][nqt][NJ] k-side partials: gluon-a | gluon-b | ghost-a
+  double* Pip;           // [RZ + RG][nqt][2] partial self-energies (sum, rounding error)
+  double* Absp;          // [RZ + RG][nqt] partial sums of |integrand|
+  double* Eq;            // [Rbp][NJ] B . T
+  // Newton
+  double* LU;            // [n][n] (used when the factors do not fit LDS)
+  int32_t* piv;          // [n]
+  int32_t* flag;         // [4] status flags written by kernels
+  double* F;             // [n]
+  double* S;             // [n]
+  double* Ft;            // [n]
+  double* St;            // [n]
+  double* dlt;           // [n]
+  double* ct;            // [n]
+  double* J;             // [n][n]
+  double* scal;          // [8] merit, ||F||_2, ||delta||_inf
+};
+
+size_t layout(const dse_params& p, Views* v, char* base);  // returns bytes
+
+// Kernel launchers (dse_kernels.hip).  All enqueue on `st`.
+hipError_t launch_dressing(const Views& v, const Phys& ph, const double* c, hipStream_t st);
+hipError_t launch_points(const Views& v, const Phys& ph, bool jacobian, hipStream_t st,
+                         hipEvent_t* ev /* nullable: [3] events before, between and after the
+                                           gluon and ghost point kernels */);
+hipError_t launch_contract(const Views& v, hipStream_t st);
+hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S,
+                           hipStream_t st);
+hipError_t launch_residual_rows(const Views& v, const Phys& ph, double* F, double* S,
+                                hipStream_t st);
+hipError_t launch_norms(const Views& v, const double* F, const double* S, const double* d,
+                        double* out, hipStream_t st);
+hipError_t launch_axpy(int n, const double* c, double rho, const double* d, double* out,
+                       hipStream_t st);
+hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x,
+                           int trans, hipStream_t st);
+
+}  // namespace dse

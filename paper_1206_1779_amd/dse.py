@@ -1,0 +1,248 @@
+"""Python binding of the C ABI in ``include/dse.h``.
+
+Argument marshalling only: PyTorch provides device memory (the workspace and
+the vectors) and the HIP stream; every computation runs in ``libdse.so``.  The
+binding refuses to run without the HIP library and a GPU -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch  # loads the HIP runtime that libdse.so binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdse.so")
+
+ABI_VERSION = 1
+MAX_N = 128
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "HIP device error", 3: "workspace too small",
+          4: "singular Newton matrix", 5: "no convergence", 6: "non-finite"}
+
+EXPORTS = [
+    "dse_params_default", "dse_workspace_bytes", "dse_init", "dse_destroy", "dse_start_guess",
+    "dse_residual", "dse_jacobian", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
+    "dse_last_error", "dse_sizes", "dse_set_timing", "dse_read_timings",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("n_z", C.c_int32), ("n_g", C.c_int32),
+        ("n_rad", C.c_int32), ("n_ir", C.c_int32), ("n_ang", C.c_int32),
+        ("precision", C.c_int32), ("reserved_", C.c_int32),
+        ("eps2", C.c_double), ("lambda2", C.c_double), ("ir_efolds", C.c_double),
+        ("alpha_mu", C.c_double), ("n_c", C.c_double), ("g0_inv", C.c_double),
+        ("z_lambda_inv", C.c_double), ("kappa", C.c_double), ("delta", C.c_double),
+        ("gamma", C.c_double),
+    ]
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("extra_iters", C.c_int32),
+                ("max_halvings", C.c_int32), ("reserved_", C.c_int32), ("step_tol", C.c_double)]
+
+
+class NewtonReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("fnorm", C.c_double),
+                ("fnorm2", C.c_double), ("fnorm_hist", C.c_double * 128),
+                ("relax_hist", C.c_double * 128), ("n_jacobians", C.c_int32),
+                ("n_residuals", C.c_int32), ("t_total_ms", C.c_double)]
+
+
+class DSEError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Loads libdse.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libdse.so not built: run `python -m paper_1206_1779_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        vp, P = C.c_void_p, C.POINTER(Params)
+        sig = {
+            "dse_params_default": (C.c_int, [P]),
+            "dse_workspace_bytes": (C.c_size_t, [P]),
+            "dse_init": (C.c_int, [P, vp, C.c_size_t, vp, C.POINTER(vp)]),
+            "dse_destroy": (C.c_int, [vp]),
+            "dse_start_guess": (C.c_int, [vp, vp]),
+            "dse_residual": (C.c_int, [vp, vp, vp, vp]),
+            "dse_jacobian": (C.c_int, [vp, vp, vp, vp]),
+            "dse_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
+            "dse_lu_solve": (C.c_int, [vp, vp, vp, vp, C.c_int32]),
+            "dse_status_string": (C.c_char_p, [C.c_int]),
+            "dse_last_error": (C.c_char_p, [vp]),
+            "dse_sizes": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]),
+            "dse_set_timing": (C.c_int, [vp, C.c_int32]),
+            "dse_read_timings": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def params(**kw) -> Params:
+    """dse_params_default() overridden by keyword arguments."""
+    p = Params()
+    load().dse_params_default(C.byref(p))
+    names = {f[0] for f in Params._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise KeyError("unknown parameter %r" % k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+@dataclass
+class NewtonResult:
+    c: torch.Tensor
+    status: int
+    iters: int
+    fnorm: float
+    fnorm2: float
+    fnorm_hist: list = field(default_factory=list)
+    relax_hist: list = field(default_factory=list)
+    n_jacobians: int = 0
+    n_residuals: int = 0
+    t_total_ms: float = 0.0
+
+
+class Solver:
+    """One context of the HIP solver on one device and stream.
+
+    Buffers are torch tensors (float64, on the context's device); the
+    workspace is allocated here once, as a uint8 tensor."""
+
+    def __init__(self, device="cuda", stream: torch.cuda.Stream | None = None, **kw):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP solver needs a GPU")
+        self.lib = load()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.p = params(**kw)
+        nbytes = self.lib.dse_workspace_bytes(C.byref(self.p))
+        if nbytes == 0:
+            h = C.c_void_p()
+            st = self.lib.dse_init(C.byref(self.p), None, 0, None, C.byref(h))
+            raise DSEError(st, self.lib.dse_last_error(None).decode())
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            h = C.c_void_p()
+            st = self.lib.dse_init(C.byref(self.p), C.c_void_p(self._ws_ptr), nbytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st:
+            raise DSEError(st, self.lib.dse_last_error(None).decode())
+        self.h = h
+        self.n = self.p.n_z + self.p.n_g
+
+    # ---------------------------------------------------------------- helpers
+    def _check(self, st):
+        if st:
+            raise DSEError(st, self.lib.dse_last_error(self.h).decode())
+
+    def _vec(self, x=None):
+        if x is None:
+            return torch.empty(self.n, dtype=torch.float64, device=self.device)
+        x = torch.as_tensor(x, dtype=torch.float64)
+        if x.device != self.device:
+            x = x.to(self.device)
+        if x.shape != (self.n,):
+            raise ValueError("expected a vector of length %d" % self.n)
+        return x.contiguous()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dse_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------- API
+    def start_guess(self) -> torch.Tensor:
+        c = self._vec()
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_start_guess(self.h, _ptr(c)))
+        return c
+
+    def residual(self, c, with_scale: bool = False):
+        c = self._vec(c)
+        F = self._vec()
+        S = self._vec() if with_scale else None
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_residual(self.h, _ptr(c), _ptr(F), _ptr(S)))
+        return (F, S) if with_scale else F
+
+    def jacobian(self, c, with_F: bool = True):
+        c = self._vec(c)
+        J = torch.empty(self.n, self.n, dtype=torch.float64, device=self.device)
+        F = self._vec() if with_F else None
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_jacobian(self.h, _ptr(c), _ptr(J), _ptr(F)))
+        return (J, F) if with_F else J
+
+    def lu_solve(self, J, b, trans: bool = False) -> torch.Tensor:
+        J = torch.as_tensor(J, dtype=torch.float64).to(self.device).contiguous()
+        b = self._vec(b)
+        x = self._vec()
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_lu_solve(self.h, _ptr(J), _ptr(b), _ptr(x), 1 if trans else 0))
+        return x
+
+    def newton(self, c0=None, tol=1e-10, max_iter=60, extra_iters=0, max_halvings=30,
+               step_tol=1e-14, raise_on_error: bool = True) -> NewtonResult:
+        c = self.start_guess() if c0 is None else self._vec(c0).clone()
+        o = NewtonOpts(tol=tol, max_iter=max_iter, extra_iters=extra_iters,
+                       max_halvings=max_halvings, step_tol=step_tol)
+        rep = NewtonReport()
+        with torch.cuda.device(self.device):
+            st = self.lib.dse_newton_solve(self.h, _ptr(c), C.byref(o), C.byref(rep))
+        if st and raise_on_error:
+            self._check(st)
+        return NewtonResult(c=c, status=rep.status, iters=rep.iters, fnorm=rep.fnorm,
+                            fnorm2=rep.fnorm2, fnorm_hist=list(rep.fnorm_hist[: rep.iters + 1]),
+                            relax_hist=list(rep.relax_hist[: rep.iters]),
+                            n_jacobians=rep.n_jacobians, n_residuals=rep.n_residuals,
+                            t_total_ms=rep.t_total_ms)
+
+    def set_timing(self, on: bool = True):
+        self._check(self.lib.dse_set_timing(self.h, 1 if on else 0))
+
+    def read_timings(self):
+        """Average device ms per dse_jacobian since set_timing(True):
+        dressing, gluon points, ghost points, contraction, assembly; and the count."""
+        out = (C.c_double * 5)()
+        cnt = C.c_int32()
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_read_timings(self.h, out, C.byref(cnt)))
+        return list(out), cnt.value
+
+    def sizes(self):
+        n, nr, na = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.dse_sizes(self.h, C.byref(n), C.byref(nr), C.byref(na)))
+        return n.value, nr.value, na.value

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances (derived from the arithmetic, see the design notes):
+  F   |F_gpu - F_ref| <= 1e-13 S_r per row, S_r = sum of |terms| in F_r
+      (the two sides sum Q*K terms in different orders, the oracle with
+      compensation; rounding is a few ulp of S_r);
+  S   relative 1e-12 (a sum of positive terms);
+  J   per row: max_c |J_gpu - J_ref| <= 1e-11 max_c |J_ref|, and normwise
+      ||J_gpu - J_ref||_F <= 1e-12 ||J_ref||_F;
+  c*  converged coefficients: ||c_gpu - c_ref||_inf <= u || |J^{-1}| S ||_inf
+      (u = 2^-53): the largest change of the root that a perturbation of every
+      term of every row by one unit roundoff can cause (componentwise
+      condition).  Both sides are iterated to their rounding floor; jittering
+      the oracle's own quadrature weights by one ulp moves c* by about a tenth
+      of this bound (1.6e-12 relative at N=16, 4.7e-11 at N=64), so a flat
+      1e-12 is below the discrete problem's own floor at N=64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dse():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1206_1779_amd import dse as d
+    d.load()
+    return d
+
+
+def _both(ref, dse, cfg):
+    return ref.params(**cfg), dse.Solver(**cfg)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+SMALL = [
+    ("cfg1", workloads.config("cfg1")),
+    ("ragged", workloads.config("cfg1", n_z=10, n_g=13, n_rad=70, n_ir=9, n_ang=13, g0_inv=0.05)),
+    ("uneven48", workloads.config("cfg1", n_z=48, n_g=20, n_rad=100, n_ir=28, n_ang=20, g0_inv=0.2)),
+    ("tiny", workloads.config("cfg1", n_z=1, n_g=1, n_rad=3, n_ir=0, n_ang=1, g0_inv=0.5)),
+    ("n128", workloads.config("cfg1", n_z=128, n_g=100, n_rad=60, n_ir=8, n_ang=10, g0_inv=0.1)),
+]
+
+
+@pytest.mark.parametrize("name,cfg", SMALL, ids=[s[0] for s in SMALL])
+def test_residual_and_jacobian_parity_small(ref, dse, name, cfg):
+    _note("parity small %s" % name)
+    p, s = _both(ref, dse, cfg)
+    c0 = ref.start_guess(p)
+    for k, c in enumerate([c0, c0 + workloads.perturbation(p.n_z, p.n_g, 0.05, seed=17)]):
+        _note("  point %d" % k)
+        Fr = ref.residual(p, c)
+        Sr = ref.residual_scale(p, c)
+        Jr = ref.jacobian(p, c)
+        Fg, Sg = s.residual(c, with_scale=True)
+        Jg, Fg2 = s.jacobian(c)
+        Fg, Sg, Jg, Fg2 = map(_np, (Fg, Sg, Jg, Fg2))
+        assert np.all(np.abs(Fg - Fr) <= 1e-13 * Sr), np.max(np.abs(Fg - Fr) / Sr)
+        assert np.all(np.abs(Fg2 - Fr) <= 1e-13 * Sr)
+        assert np.max(np.abs(Sg - Sr) / Sr) < 1e-12
+        rowmax = np.max(np.abs(Jr), axis=1)
+        err = np.max(np.abs(Jg - Jr), axis=1)
+        assert np.all(err <= 1e-11 * rowmax), np.max(err / rowmax)
+        assert np.linalg.norm(Jg - Jr) <= 1e-12 * np.linalg.norm(Jr)
+
+
+def test_cfg2_parity_full_size(ref, dse):
+    """N = 64 per function, 256+64 radial x 64 angular: every entry."""
+    _note("parity cfg2")
+    cfg = workloads.config("cfg2")
+    p, s = _both(ref, dse, cfg)
+    c = ref.start_guess(p) + workloads.perturbation(p.n_z, p.n_g, 0.02, seed=5)
+    Jr, Fr = ref.jacobian(p, c, with_F=True)
+    Sr = ref.residual_scale(p, c)
+    Jg, Fg = s.jacobian(c)
+    Jg, Fg = _np(Jg), _np(Fg)
+    assert np.all(np.abs(Fg - Fr) <= 1e-13 * Sr), np.max(np.abs(Fg - Fr) / Sr)
+    rowmax = np.max(np.abs(Jr), axis=1)
+    assert np.all(np.max(np.abs(Jg - Jr), axis=1) <= 1e-11 * rowmax)
+    assert np.linalg.norm(Jg - Jr) <= 1e-12 * np.linalg.norm(Jr)
+
+
+def test_cfg3_sampled_rows_full_size(ref, dse):
+    """N = 128 per function, 1024+256 radial x 128 angular: sampled rows of J
+    (the oracle computes them one by one) and every F entry."""
+    _note("parity cfg3 sampled")
+    cfg = workloads.config("cfg3")
+    p, s = _both(ref, dse, cfg)
+    c = ref.start_guess(p)
+    rows = [0, 1, 63, 127, 128, 129, 200, 255]
+    Jr = ref.jacobian(p, c, rows=rows)
+    Fr = ref.residual(p, c)
+    Sr = ref.residual_scale(p, c)
+    Jg, Fg = s.jacobian(c)
+    Jg, Fg = _np(Jg), _np(Fg)
+    assert np.all(np.abs(Fg - Fr) <= 1e-13 * Sr), np.max(np.abs(Fg - Fr) / Sr)
+    for r in rows:
+        rm = np.max(np.abs(Jr[r]))
+        assert np.max(np.abs(Jg[r] - Jr[r])) <= 1e-11 * rm, (r, np.max(np.abs(Jg[r] - Jr[r])) / rm)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_newton_parity(ref, dse, name):
+    _note("newton %s" % name)
+    cfg = workloads.config(name)
+    p, s = _both(ref, dse, cfg)
+    cr, rr = ref.newton(p, extra_iters=2)
+    res = s.newton(extra_iters=2)
+    cg = _np(res.c)
+    assert rr["status"] == 0 and res.status == 0
+    assert res.fnorm < 1e-13
+    assert abs(res.iters - rr["iters"]) <= 1
+    J = ref.jacobian(p, cr)
+    S = ref.residual_scale(p, cr)
+    bound = 2.0 ** -53 * np.max(np.abs(np.linalg.inv(J)) @ S)
+    err = np.max(np.abs(cg - cr))
+    _note("  max coefficient difference %.3e, bound %.3e, relative %.3e (iters gpu %d oracle %d)"
+          % (err, bound, err / np.max(np.abs(cr)), res.iters, rr["iters"]))
+    assert err <= bound
+
+
+def test_start_guess_parity(ref, dse):
+    for name in ["cfg1", "cfg2"]:
+        cfg = workloads.config(name)
+        p, s = _both(ref, dse, cfg)
+        assert np.max(np.abs(_np(s.start_guess()) - ref.start_guess(p))) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 7, 64, 128, 200])
+@pytest.mark.parametrize("trans", [False, True])
+def test_lu_solve(ref, dse, n, trans):
+    _note("lu n=%d trans=%d" % (n, trans))
+    cfg = workloads.config("cfg1", n_z=max(1, n // 2), n_g=max(1, n - n // 2)) if n > 1 else \
+        workloads.config("cfg1", n_z=1, n_g=1)
+    s = dse.Solver(**cfg)
+    nn = s.n
+    rng = np.random.default_rng(nn)
+    A = rng.standard_normal((nn, nn)) + np.diag(rng.uniform(-3, 3, nn))
+    b = rng.standard_normal(nn)
+    x = _np(s.lu_solve(A, b, trans=trans))
+    xr = ref.lu_solve(A, b, trans=trans)
+    assert np.linalg.norm(x - xr) <= 1e-12 * np.linalg.cond(A) * np.linalg.norm(xr)
+
+
+def test_lu_singular(dse):
+    import torch
+    s = dse.Solver(**workloads.config("cfg1", n_z=2, n_g=2))
+    with pytest.raises(dse.DSEError) as e:
+        s.lu_solve(torch.ones(4, 4, dtype=torch.float64), torch.ones(4, dtype=torch.float64))
+    assert e.value.status == 4
+
+
+def test_deterministic(dse):
+    s = dse.Solver(**workloads.config("cfg1", n_z=20, n_g=20))
+    c = s.start_guess()
+    J1, F1 = s.jacobian(c)
+    J2, F2 = s.jacobian(c)
+    assert bool((J1 == J2).all()) and bool((F1 == F2).all())
+
+
+def test_invalid_params_raise(dse):
+    with pytest.raises(dse.DSEError):
+        dse.Solver(**workloads.config("cfg1", n_z=200))
+
+
+def test_noconv_reports_last_iterate(ref, dse):
+    cfg = workloads.config("cfg1")
+    s = dse.Solver(**cfg)
+    res = s.newton(max_iter=2, raise_on_error=False)
+    assert res.status == 5 and res.iters == 2
+    p = ref.params(**cfg)
+    F = ref.residual(p, _np(res.c))
+    S = ref.residual_scale(p, _np(res.c))
+    assert abs(np.max(np.abs(F) / S) - res.fnorm) <= 1e-9 * res.fnorm

@@ -505,3 +505,23 @@ def test_one_loop_z_lambda_values():
     # and the pair reproduces alpha(M_Z^2) = 0.118 to the quoted digits
     mz2 = GOLD["alpha_mz"]["mz_gev"] ** 2
     assert abs(1 / (1 + om * math.log(mz2 / mu2)) - GOLD["alpha_mz"]["value"]) < 2e-3
+
+
+def test_root_rounding_floor_below_condition_bound(ref):
+    """Changing every quadrature weight by one ulp moves the converged
+    coefficients by at most u || |J^{-1}| S ||_inf, the bound the GPU parity
+    test uses for c* (and by more than 1e-13 relative: the floor is real)."""
+    p = ref.params(**workloads.config("cfg1"))
+    c0, _ = ref.newton(p, extra_iters=2)
+    J = ref.jacobian(p, c0)
+    S = ref.residual_scale(p, c0)
+    bound = 2.0 ** -53 * np.max(np.abs(np.linalg.inv(J)) @ S)
+    try:
+        ref.set_jitter(2.0 ** -52)
+        c1, r = ref.newton(p, extra_iters=2)
+    finally:
+        ref.set_jitter(0.0)
+    shift = np.max(np.abs(c1 - c0))
+    assert r["status"] == 0
+    assert shift <= bound
+    assert shift > 1e-13 * np.max(np.abs(c0))
