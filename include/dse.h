@@ -163,6 +163,22 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
 dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, double* d_x,
                         int32_t trans);
 
+/* Vector-Jacobian products at c for a weight vector u (length n):
+ *   d_uJ[k]     = sum_r u_r dF_r/dc_k                     (n entries; nullable)
+ *   d_utheta[0] = sum_r u_r dF_r/d alpha_mu                (3 entries; nullable)
+ *   d_utheta[1] = sum_r u_r dF_r/d g0_inv,  d_utheta[2] = sum_r u_r dF_r/d z_lambda_inv
+ * alpha_mu enters F through the prefactor g^2 N_c/(2 pi)^3 of both
+ * self-energies and through omega = 11 N_c alpha/(12 pi) in the UV
+ * extrapolation of the dressings (Sec. 2); G(x_G)^{-1} and Z(x_Z)^{-1} enter
+ * the MOM-subtracted equations linearly (Sec. 3).  One weighted pass of the
+ * point kernels; with d_uJ == NULL the k- and q-side derivative sums are
+ * skipped (the cost of one residual).  Enqueued on the context's stream. */
+dse_status dse_vjp(dse_ctx* ctx, const double* d_c, const double* d_u, double* d_uJ, double* d_utheta);
+
+/* Changes alpha(mu^2), G(x_G)^{-1} and Z(x_Z)^{-1} of an existing context (the
+ * grid and tables do not depend on them).  Validated like dse_init. */
+dse_status dse_set_physics(dse_ctx* ctx, double alpha_mu, double g0_inv, double z_lambda_inv);
+
 const char* dse_status_string(dse_status s);
 /* Message of the last failed call on ctx (or of the last failed dse_init when
  * ctx is NULL). */

@@ -170,6 +170,8 @@ dse::Phys make_phys(const dse_params& p) {
   ph.gamma = p.gamma;
   ph.g0_inv = p.g0_inv;
   ph.z_lambda_inv = p.z_lambda_inv;
+  ph.inv_alpha = 1.0 / p.alpha_mu;
+  ph.omega_per_alpha = 11.0 * p.n_c / (12.0 * kPi);
   return ph;
 }
 
@@ -191,6 +193,10 @@ size_t layout(const dse_params& p, Views* v, char* base) {
   t.RZ = p.n_z + 1;
   t.RG = p.n_g + 1;
   t.nqt = t.Qp / 64;
+  // angular slices: enough blocks to fill the chip (about four per CU for the
+  // larger row kind), at least two angles per lane
+  t.KS = 1;
+  while (t.KS < 8 && (t.RZ > t.RG ? t.RZ : t.RG) * t.nqt * t.KS < 1024 && t.Kp / (4 * t.KS * 2) >= 2) t.KS *= 2;
   t.Rb = 2 * t.RZ + t.RG;
   t.Rbp = pad_up(t.Rb, 16);
   size_t off = 0;
@@ -210,12 +216,15 @@ size_t layout(const dse_params& p, Views* v, char* base) {
   t.xrow = (double*)take((t.RZ + t.RG) * d);
   t.lnX = (double*)take(t.n * d);
   t.ang = (double*)take(5 * t.Kp * d);
-  t.Bm = (double*)take((size_t)t.Rbp * t.Qp * d);
-  t.Dp = (double*)take((size_t)(2 * t.RZ + t.RG) * t.nqt * t.NJ * d);
-  t.Pip = (double*)take((size_t)2 * (t.RZ + t.RG) * t.nqt * d);
-  t.Absp = (double*)take((size_t)(t.RZ + t.RG) * t.nqt * d);
+  t.Bm = (double*)take((size_t)t.KS * t.Rbp * t.Qp * d);
+  t.Dp = (double*)take((size_t)(2 * t.RZ + t.RG) * t.nqt * t.KS * t.NJ * d);
+  t.Pip = (double*)take((size_t)2 * (t.RZ + t.RG) * t.nqt * t.KS * d);
+  t.Absp = (double*)take((size_t)(t.RZ + t.RG) * t.nqt * t.KS * d);
   t.Eq = (double*)take((size_t)t.Rbp * t.NJ * d);
-  t.LU = (double*)take((size_t)t.n * t.n * d);
+  t.Dgh = (double*)take((size_t)t.RG * t.NJ * d);
+  t.rw = (double*)take((size_t)(t.RZ + t.RG) * d);
+  const size_t np16 = (size_t)(t.n + 15) / 16 * 16;
+  t.LU = (double*)take(np16 * (np16 + 1) * d);  // padded [A | b] when it does not fit LDS
   t.piv = (int32_t*)take(t.n * sizeof(int32_t));
   t.flag = (int32_t*)take(4 * sizeof(int32_t));
   t.F = (double*)take(t.n * d);
@@ -293,7 +302,7 @@ dse_status build_tables(dse_ctx* ctx) {
       ang[v.Kp + k] = 0.5;  // padding angle: zero weight
     }
   }
-  std::vector<double> zeros((size_t)v.Rbp * v.Qp, 0.0);
+  std::vector<double> zeros((size_t)v.KS * v.Rbp * v.Qp, 0.0);
   hipStream_t st = ctx->st;
   HIP_TRY(ctx, hipMemcpyAsync(v.y, y.data(), v.Qp * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(v.W, W.data(), v.Qp * 8, hipMemcpyHostToDevice, st));
@@ -324,7 +333,7 @@ struct DeviceGuard {
 dse_status eval_residual(dse_ctx* ctx, const double* c, double* F, double* S) {
   const dse::Views& v = ctx->v;
   HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, c, ctx->st));
-  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, false, ctx->st, nullptr));
+  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, 0, ctx->st, nullptr));
   HIP_TRY(ctx, dse::launch_residual_rows(v, ctx->ph, F, S, ctx->st));
   return DSE_OK;
 }
@@ -343,7 +352,7 @@ dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, do
   }
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[0], ctx->st));
   HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, c, ctx->st));
-  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, true, ctx->st, ev ? ev + 1 : nullptr));
+  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, 1, ctx->st, ev ? ev + 1 : nullptr));
   HIP_TRY(ctx, dse::launch_contract(v, ctx->st));
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[4], ctx->st));
   HIP_TRY(ctx, dse::launch_assemble(v, ctx->ph, J, F, S, ctx->st));
@@ -566,6 +575,35 @@ dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, doub
   HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
   if (flag == DSE_E_SINGULAR) { set_err(ctx->err, "zero pivot"); return DSE_E_SINGULAR; }
+  return DSE_OK;
+}
+
+dse_status dse_vjp(dse_ctx* ctx, const double* d_c, const double* d_u, double* d_uJ, double* d_utheta) {
+  if (!ctx) return DSE_E_INVALID;
+  if (!d_c || !d_u || (!d_uJ && !d_utheta)) {
+    set_err(ctx->err, "d_c, d_u and one of d_uJ, d_utheta are required");
+    return DSE_E_INVALID;
+  }
+  DeviceGuard dg(ctx->device);
+  const dse::Views& v = ctx->v;
+  HIP_TRY(ctx, dse::launch_row_weights(v, d_u, ctx->st));
+  HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, d_c, ctx->st));
+  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, d_uJ ? 2 : 3, ctx->st, nullptr));
+  if (d_uJ) HIP_TRY(ctx, dse::launch_contract(v, ctx->st));
+  HIP_TRY(ctx, dse::launch_vjp_reduce(v, d_u, d_uJ, d_utheta, ctx->st));
+  return DSE_OK;
+}
+
+dse_status dse_set_physics(dse_ctx* ctx, double alpha_mu, double g0_inv, double z_lambda_inv) {
+  if (!ctx) return DSE_E_INVALID;
+  dse_params p = ctx->p;
+  p.alpha_mu = alpha_mu;
+  p.g0_inv = g0_inv;
+  p.z_lambda_inv = z_lambda_inv;
+  dse_status s = validate(&p, ctx->err);
+  if (s != DSE_OK) return s;
+  ctx->p = p;
+  ctx->ph = make_phys(p);
   return DSE_OK;
 }
 

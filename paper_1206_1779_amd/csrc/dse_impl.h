@@ -35,6 +35,8 @@ struct Phys {
   double ln_eps2, ln_lam2;
   double kappa, delta, gamma;
   double g0_inv, z_lambda_inv;
+  double inv_alpha;        // 1 / alpha(mu^2)
+  double omega_per_alpha;  // d omega / d alpha = 11 N_c / (12 pi)
 };
 
 // Device views into the caller's workspace.
@@ -43,7 +45,8 @@ struct Views {
   int NJ;                // padded order
   int Q, Qp, K, Kp;      // radial / angular nodes and their padded counts
   int RZ, RG;            // gluon rows (n_z + subtraction at Lambda^2), ghost rows (n_g + x = 0)
-  int nqt;               // q-tiles per row used by the point kernels (Qp / 64 * 4 max)
+  int nqt;               // radial tiles of 64 nodes per row (Qp / 64)
+  int KS;                // angular slices: point-kernel blocks per (row, radial tile)
   int Rb, Rbp;           // rows of the B matrix (2 RZ + RG) and padded to 16
   // tables
   double* coef;          // [2][NJ] a then b, zero padded, j = 0 term halved
@@ -57,13 +60,15 @@ struct Views {
   double* lnX;           // [n] ln Z (gluon rows) / ln G (ghost rows) at x_r
   double* ang;           // [5][Kp] cos, sin^2(theta/2), v sin^2, v sin^4, sin^2
   // per assembly
-  double* Bm;            // [Rbp][Qp] angular sums: rows gluon-a | gluon-b | ghost-b
-  double* Dp;            // [3][RZ or RG][nqt][NJ] k-side partials: gluon-a | gluon-b | ghost-a
-  double* Pip;           // [RZ + RG][nqt][2] partial self-energies (sum, rounding error)
-  double* Absp;          // [RZ + RG][nqt] partial sums of |integrand|
-  double* Eq;            // [Rbp][NJ] B . T
+  double* Bm;            // [KS][Rbp][Qp] angular sums per slice: rows gluon-a | gluon-b | ghost-b
+  double* Dp;            // [3][RZ or RG][nqt*KS][NJ] k-side partials: gluon-a | gluon-b | ghost-a
+  double* Pip;           // [RZ + RG][nqt*KS][2] partial self-energies (sum, rounding error)
+  double* Absp;          // [RZ + RG][nqt*KS] partial sums of |integrand|
+  double* Eq;            // [Rbp][NJ] B . T (+ k-side sums for the gluon rows)
+  double* Dgh;           // [RG][NJ] k-side sums of the ghost rows (target a)
+  double* rw;            // [RZ + RG] row weights of a vector-Jacobian product
   // Newton
-  double* LU;            // [n][n] (used when the factors do not fit LDS)
+  double* LU;            // [np][np+1], np = 16 ceil(n/16): padded factors of [A | b] when they do not fit LDS
   int32_t* piv;          // [n]
   int32_t* flag;         // [4] status flags written by kernels
   double* F;             // [n]
@@ -80,10 +85,13 @@ size_t layout(const dse_params& p, Views* v, char* base);  // returns bytes
 
 // Kernel launchers (dse_kernels.hip).  All enqueue on `st`.
 hipError_t launch_dressing(const Views& v, const Phys& ph, const double* c, hipStream_t st);
-hipError_t launch_points(const Views& v, const Phys& ph, bool jacobian, hipStream_t st,
+// mode: 0 residual, 1 Jacobian, 2 vector-Jacobian product, 3 parameter VJP
+hipError_t launch_points(const Views& v, const Phys& ph, int mode, hipStream_t st,
                          hipEvent_t* ev /* nullable: [3] events before, between and after the
                                            gluon and ghost point kernels */);
 hipError_t launch_contract(const Views& v, hipStream_t st);
+hipError_t launch_row_weights(const Views& v, const double* u, hipStream_t st);
+hipError_t launch_vjp_reduce(const Views& v, const double* u, double* uJ, double* uth, hipStream_t st);
 hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S,
                            hipStream_t st);
 hipError_t launch_residual_rows(const Views& v, const Phys& ph, double* F, double* S,

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <utility>
+
 #include "dse_impl.h"
 
 namespace dse {
@@ -111,24 +113,80 @@ __global__ __launch_bounds__(256) void dressing_kernel(Views v, Phys ph, const d
 }
 
 // --------------------------------------------------------------------------
+// Reduce-scatter of NV values per lane over the lanes that share a slice
+// (lane bits log2(G) .. 5).  While the count is even a stage halves it: the
+// lane keeps one half and sends the other to its partner; an odd count falls
+// back to a butterfly all-reduce (then only the lane with the bit clear
+// writes).  On return vals[0 .. slice_count) hold complete sums for indices
+// base .. base + slice_count - 1.
+template <int NV, int G>
+__host__ __device__ constexpr int slice_count() {
+  int c = NV;
+  for (int o = G; o < 64; o <<= 1)
+    if (c % 2 == 0) c /= 2;
+  return c;
+}
+
+template <int CNT, int O>
+__device__ __forceinline__ void slice_stage(double* vals, int lane, int& base, bool& writer) {
+  if constexpr (O < 64) {
+    if constexpr (CNT % 2 == 0) {
+      constexpr int H = CNT / 2;
+      const bool hi = (lane & O) != 0;
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        const double send = hi ? vals[i] : vals[i + H];
+        const double keep = hi ? vals[i + H] : vals[i];
+        vals[i] = keep + __shfl_xor(send, O, 64);
+      }
+      if (hi) base += H;
+      slice_stage<H, O * 2>(vals, lane, base, writer);
+    } else {
+#pragma unroll
+      for (int i = 0; i < CNT; ++i) vals[i] += __shfl_xor(vals[i], O, 64);
+      if (lane & O) writer = false;
+      slice_stage<CNT, O * 2>(vals, lane, base, writer);
+    }
+  }
+}
+
+template <int NV, int G>
+__device__ __forceinline__ void slice_reduce(double* vals, int lane, int& base, bool& writer) {
+  slice_stage<NV, G>(vals, lane, base, writer);
+}
+
+// --------------------------------------------------------------------------
 // The fused point kernel.  Block = one row x 64 radial nodes; wave w takes the
 // angles k = w, w+4, ...; lane = radial node.  Pass 1 (every lane, own point):
 // recurrence + series with wave-uniform coefficients.  Pass 2 (Jacobian only):
 // a group of G lanes shares its G points; member m accumulates
 // j in [m JT, (m+1) JT) for all G points, starting the recurrence from
 // (T_{m JT - 1}, T_{m JT}) saved in pass 1.
-template <int KIND, int NJ, bool JAC>
+//
+// MODE: 0 residual (Pi and sum|.| per tile); 1 Jacobian (also B and D);
+// 2 vector-Jacobian product (every integrand and its derivatives weighted by
+// the row weight rw[row]: B and D then sum to u^T dF/dc; the pair slots of
+// Pip carry d Pi / d alpha, weighted); 3 parameter VJP only (weighted
+// d Pi / d alpha, no B, no D).
+enum { MODE_RES = 0, MODE_JAC = 1, MODE_VJP = 2, MODE_VTH = 3 };
+
+template <int KIND, int NJ, int MODE>
 __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   using TL = Tile<KIND, NJ>;
   constexpr int G = TL::G;
   constexpr int JT = TL::JT;
   constexpr int NT = KIND == GLUON ? 2 : 1;  // k-side targets
+  constexpr bool JAC = MODE == MODE_JAC || MODE == MODE_VJP;  // B and D wanted
+  constexpr bool WEIGHTED = MODE == MODE_VJP || MODE == MODE_VTH;
 
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
-  const int row = blockIdx.x / v.nqt;
-  const int qt = blockIdx.x - row * v.nqt;
+  const int KS = v.KS;
+  const int ntile = v.nqt * KS;                   // partial tiles per row
+  const int row = blockIdx.x / ntile;
+  const int tile = blockIdx.x - row * ntile;      // = qt * KS + ks
+  const int qt = tile / KS, ks = tile - qt * KS;
   const int q = qt * 64 + lane;
   const int growrow = KIND == GLUON ? row : v.RZ + row;  // index into xrow / Pip
 
@@ -163,6 +221,7 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   const double* __restrict__ cb = v.coef + NJ;
   const double* __restrict__ ang = v.ang;
   const int Kp = v.Kp;
+  const double rw = WEIGHTED ? v.rw[growrow] : 1.0;
 
   double pi_s = 0.0, pi_c = 0.0, abs_acc = 0.0, Ba = 0.0, Bb = 0.0;
   double Da[JAC ? JT : 1], Db[JAC && NT == 2 ? JT : 1];
@@ -172,7 +231,7 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   }
   const int member = lane & (G - 1);
 
-  for (int k = wave; k < Kp; k += 4) {
+  for (int k = ks * 4 + wave; k < Kp; k += 4 * KS) {
     const double ck = ang[k];
     const double s2h = ang[Kp + k];
     const double wk = KIND == GLUON ? ang[2 * Kp + k] : ang[3 * Kp + k];
@@ -198,14 +257,17 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
       Tp = Tc;
       Tc = Tn;
     }
-    double XZ = 0.0, XG = 0.0;
+    double XZ = 0.0, XG = 0.0, dXa = 0.0;  // dXa: d ln(1 + omega l) / d alpha (UV)
     if (lz < ph.ln_eps2) {
       XZ = 2.0 * ph.kappa * (lz - ph.ln_eps2);
       XG = -ph.kappa * (lz - ph.ln_eps2);
     } else if (lz > ph.ln_lam2) {
-      const double L = log(fma(ph.omega, lz - ph.ln_lam2, 1.0));
+      const double l = lz - ph.ln_lam2;
+      const double arg = fma(ph.omega, l, 1.0);
+      const double L = log(arg);
       XZ = ph.gamma * L;
       XG = ph.delta * L;
+      if (WEIGHTED) dXa = ph.omega_per_alpha * l / arg;
     }
     const double lZz = sa + XZ;
 
@@ -222,15 +284,30 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
       const double om = pref * wk;
       const double tq = om * Qk * Fgl;
       const double tm = om * Mk * Fgh;
-      two_sum_add(pi_s, pi_c, tq + tm);
-      abs_acc += fabs(tq) + fabs(tm);
       Pa = tq * ph.e2;           // d integrand / d ln Z (at y or at z)
       Pb = fma(tq, ph.e1, tm);   // d integrand / d ln G (at y or at z)
+      if (WEIGHTED) {
+        // d integrand / d alpha: linear through C, and through omega in the
+        // UV extrapolation of ln Z(z), ln G(z)
+        const double da = (tq + tm) * ph.inv_alpha + (Pa * ph.gamma + Pb * ph.delta) * dXa;
+        two_sum_add(pi_s, pi_c, rw * da);
+        Pa *= rw;
+        Pb *= rw;
+      } else {
+        two_sum_add(pi_s, pi_c, tq + tm);
+        abs_acc += fabs(tq) + fabs(tm);
+      }
       if (JAC) { Ba += Pa; Bb += Pb; }
     } else {
-      const double val = pref * wk * exp(lGy + lZz - 2.0 * lz);  // rho G(y) Z(z) / z^2
-      two_sum_add(pi_s, pi_c, val);
-      abs_acc += fabs(val);
+      double val = pref * wk * exp(lGy + lZz - 2.0 * lz);  // rho G(y) Z(z) / z^2
+      if (WEIGHTED) {
+        const double da = val * ph.inv_alpha + val * ph.gamma * dXa;
+        two_sum_add(pi_s, pi_c, rw * da);
+        val *= rw;
+      } else {
+        two_sum_add(pi_s, pi_c, val);
+        abs_acc += fabs(val);
+      }
       Pa = val;                  // k-side: d / d ln Z(z)
       Pb = val;
       if (JAC) Bb += val;        // q-side: d / d ln G(y)
@@ -284,7 +361,7 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
     double ps = red[0][0], pc = red[1][0];
     for (int w = 1; w < 4; ++w) { two_sum_add(ps, pc, red[0][w]); pc += red[1][w]; }
     const double a = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
-    const size_t idx = (size_t)growrow * v.nqt + qt;
+    const size_t idx = (size_t)growrow * ntile + tile;
     v.Pip[2 * idx] = ps;
     v.Pip[2 * idx + 1] = pc;
     v.Absp[idx] = a;
@@ -295,60 +372,90 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   __shared__ double bs[2][4][64];
   bs[0][wave][lane] = Ba;
   bs[1][wave][lane] = Bb;
-  // ---- k-side: reduce each coefficient over the lanes of the wave that hold
-  // the same slice, then over the waves through LDS
-  __shared__ double ds[4][NT][NJ];
+  // ---- k-side: reduce-scatter over the lanes that hold the same slice, then
+  // over the waves through LDS
+  __shared__ double ds[4][NT * NJ];
+  {
+    double vals[NT * JT];
 #pragma unroll
-  for (int jj = 0; jj < JT; ++jj) {
-    double a = Da[jj];
-    double b = NT == 2 ? Db[jj] : 0.0;
-#pragma unroll
-    for (int o = 32; o >= G; o >>= 1) {
-      a += __shfl_xor(a, o, 64);
-      if (NT == 2) b += __shfl_xor(b, o, 64);
+    for (int jj = 0; jj < JT; ++jj) {
+      vals[jj] = Da[jj];
+      if (NT == 2) vals[JT + jj] = Db[jj];
     }
-    if (lane < G) {
-      ds[wave][0][lane * JT + jj] = a;
-      if (NT == 2) ds[wave][NT - 1][lane * JT + jj] = b;
+    int base = 0;        // index (within this lane's NT*JT values) of vals[0]
+    bool writer = true;  // one lane of each group of equal partial sums writes
+    slice_reduce<NT * JT, G>(vals, lane, base, writer);
+    constexpr int CNT = slice_count<NT * JT, G>();
+    if (writer) {
+#pragma unroll
+      for (int i = 0; i < CNT; ++i) {
+        const int idx = base + i;           // 0 .. NT*JT-1
+        const int tg = idx / JT, jj = idx - tg * JT;
+        ds[wave][tg * NJ + member * JT + jj] = vals[i];
+      }
     }
   }
   __syncthreads();
   if (t < 64) {
     const double sa_ = ((bs[0][0][t] + bs[0][1][t]) + bs[0][2][t]) + bs[0][3][t];
     const double sb_ = ((bs[1][0][t] + bs[1][1][t]) + bs[1][2][t]) + bs[1][3][t];
+    double* Bk = v.Bm + (size_t)ks * v.Rbp * v.Qp;
     if (KIND == GLUON) {
-      v.Bm[(size_t)row * v.Qp + qt * 64 + t] = sa_;
-      v.Bm[(size_t)(v.RZ + row) * v.Qp + qt * 64 + t] = sb_;
+      Bk[(size_t)row * v.Qp + qt * 64 + t] = sa_;
+      Bk[(size_t)(v.RZ + row) * v.Qp + qt * 64 + t] = sb_;
     } else {
-      v.Bm[(size_t)(2 * v.RZ + row) * v.Qp + qt * 64 + t] = sb_;
+      Bk[(size_t)(2 * v.RZ + row) * v.Qp + qt * 64 + t] = sb_;
     }
   }
   for (int o = t; o < NT * NJ; o += 256) {
     const int tg = o / NJ, j = o - tg * NJ;
-    double s = ((ds[0][tg][j] + ds[1][tg][j]) + ds[2][tg][j]) + ds[3][tg][j];
-    if (j == 0) s *= 0.5;  // Tilde-T_0 = 1/2
-    int grp = KIND == GLUON ? tg : 2;
-    size_t base = (size_t)grp * v.RZ * v.nqt * NJ;
-    v.Dp[base + ((size_t)row * v.nqt + qt) * NJ + j] = s;
+    double sum = ((ds[0][o] + ds[1][o]) + ds[2][o]) + ds[3][o];
+    if (j == 0) sum *= 0.5;  // Tilde-T_0 = 1/2
+    const int grp = KIND == GLUON ? tg : 2;
+    const size_t base = (size_t)grp * v.RZ * ntile * NJ;
+    v.Dp[base + ((size_t)row * ntile + tile) * NJ + j] = sum;
   }
 }
 
 // --------------------------------------------------------------------------
-// Eq = B . T on the FP64 matrix cores.  Block = one 16 x 16 tile of Eq; the
-// four waves split the radial sum and meet in LDS.
+// Eq = B . T on the FP64 matrix cores, plus the k-side sums.  Blocks with
+// blockIdx.x < Rbp/16 compute one 16 x 16 tile of Eq (the four waves split
+// the radial sum and meet in LDS) and add, for gluon rows, the k-side partial
+// sums of the same target; the remaining blocks reduce the ghost rows'
+// k-side partials into Dgh.  Every sum runs in a fixed order.
 __global__ __launch_bounds__(256) void contract_kernel(Views v) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int r0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
   const int Qp = v.Qp, NJ = v.NJ;
+  const int ntile = v.nqt * v.KS;
+  const size_t dstride = (size_t)ntile * NJ;
+  const int ntiles_r = v.Rbp / 16;
+  if ((int)blockIdx.x >= ntiles_r) {
+    // ghost rows, k-side (target a): Dgh[row][j] = sum over tiles
+    const int row0 = ((int)blockIdx.x - ntiles_r) * 16;
+    const double* D = v.Dp + (size_t)2 * v.RZ * dstride;
+    for (int e = t; e < 16 * 16; e += 256) {
+      const int r = row0 + (e >> 4), j = blockIdx.y * 16 + (e & 15);
+      if (r < v.RG) {
+        const double* src = D + (size_t)r * dstride + j;
+        double sum = 0.0;
+        for (int k = 0; k < ntile; ++k) sum += src[(size_t)k * NJ];
+        v.Dgh[(size_t)r * NJ + j] = sum;
+      }
+    }
+    return;
+  }
+  const int r0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
   const int qper = Qp / 4;
   const int qbeg = wave * qper;
   const int i = lane & 15, kk = lane >> 4;
   typedef double d4 __attribute__((ext_vector_type(4)));
   d4 acc = {0.0, 0.0, 0.0, 0.0};
   const double* A = v.Bm + (size_t)(r0 + i) * Qp + kk;
+  const size_t kstride = (size_t)v.Rbp * Qp;  // angular slices of B
   const double* B = v.Ttab + (size_t)kk * NJ + j0 + i;
   for (int q = qbeg; q < qbeg + qper; q += 4) {
-    const double a = A[q];
+    double a = A[q];
+    for (int k = 1; k < v.KS; ++k) a += A[k * kstride + q];
     const double b = B[(size_t)q * NJ];
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
@@ -356,15 +463,21 @@ __global__ __launch_bounds__(256) void contract_kernel(Views v) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
   __syncthreads();
-  if (t < 64) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double s = ((part[0][r][t] + part[1][r][t]) + part[2][r][t]) + part[3][r][t];
-      // v_mfma_f64_16x16x4f64: lane l, register r holds D[l/16 + 4 r][l % 16]
-      const int row = r0 + (t >> 4) + 4 * r;
-      const int col = j0 + (t & 15);
-      v.Eq[(size_t)row * NJ + col] = s;
+  {
+    // one output element per thread: (ri, cj) of the tile; the MFMA result
+    // D[ri][cj] sits in lane (ri % 4) * 16 + cj, register ri / 4
+    // (v_mfma_f64_16x16x4f64: lane l, register r holds D[l/16 + 4 r][l % 16])
+    const int ri = t >> 4, cj = t & 15;
+    const int l = (ri & 3) * 16 + cj, rg = ri >> 2;
+    double sum = ((part[0][rg][l] + part[1][rg][l]) + part[2][rg][l]) + part[3][rg][l];
+    const int row = r0 + ri, col = j0 + cj;
+    if (row < 2 * v.RZ) {  // gluon rows: add the k-side sums of the same target
+      const double* src = v.Dp + (size_t)row * dstride + col;  // groups a, b are contiguous
+      double ds_ = 0.0;
+      for (int k = 0; k < ntile; ++k) ds_ += src[(size_t)k * NJ];
+      sum += ds_;
     }
+    v.Eq[(size_t)row * NJ + col] = sum;
   }
 }
 
@@ -375,11 +488,7 @@ __device__ __forceinline__ double sum_tiles(const double* p, int nqt) {
   for (int i = 0; i < nqt; ++i) s += p[i];
   return s;
 }
-__device__ __forceinline__ double sum_tiles_strided(const double* p, int nqt, int stride) {
-  double s = 0.0;
-  for (int i = 0; i < nqt; ++i) s += p[(size_t)i * stride];
-  return s;
-}
+
 
 // Self-energy of one row from its (sum, error) tile pairs.
 __device__ __forceinline__ double pi_row(const double* p, int nqt) {
@@ -394,10 +503,11 @@ __device__ __forceinline__ void row_residual(const Views& v, const Phys& ph, int
   const bool gl = r < v.n_z;
   const int rr = gl ? r : v.RZ + (r - v.n_z);          // row in xrow / Pip
   const int sub = gl ? v.RZ - 1 : v.RZ + v.RG - 1;      // subtraction row
-  const double pix = pi_row(v.Pip + (size_t)2 * rr * v.nqt, v.nqt);
-  const double pis = pi_row(v.Pip + (size_t)2 * sub * v.nqt, v.nqt);
-  const double abx = sum_tiles(v.Absp + (size_t)rr * v.nqt, v.nqt);
-  const double abs_ = sum_tiles(v.Absp + (size_t)sub * v.nqt, v.nqt);
+  const int nt = v.nqt * v.KS;
+  const double pix = pi_row(v.Pip + (size_t)2 * rr * nt, nt);
+  const double pis = pi_row(v.Pip + (size_t)2 * sub * nt, nt);
+  const double abx = sum_tiles(v.Absp + (size_t)rr * nt, nt);
+  const double abs_ = sum_tiles(v.Absp + (size_t)sub * nt, nt);
   const double d = exp(-v.lnX[r]);
   const double par = gl ? ph.z_lambda_inv : ph.g0_inv;
   F[r] = d - par - pix + pis;
@@ -414,44 +524,36 @@ __global__ __launch_bounds__(256) void assemble_kernel(Views v, Phys ph, double*
                                                        double* F, double* S) {
   const int r = blockIdx.x;
   const int t = threadIdx.x;
-  const int NJ = v.NJ, nqt = v.nqt, n = v.n;
+  const int NJ = v.NJ, n = v.n;
   const bool gl = r < v.n_z;
   const int i = gl ? r : r - v.n_z;
   const double d = exp(-v.lnX[r]);
   const double* Tx = v.Text + (size_t)r * NJ;
   double* Jr = J + (size_t)r * n;
-  const size_t dstride = (size_t)nqt * NJ;
   if (gl) {
     const int sub = v.RZ - 1;
-    const double* Dga = v.Dp;
-    const double* Dgb = v.Dp + (size_t)v.RZ * dstride;
+    const double* Ea = v.Eq;
+    const double* Eb = v.Eq + (size_t)v.RZ * NJ;
     for (int c = t; c < n; c += blockDim.x) {
       double val;
       if (c < v.n_z) {
-        const int j = c;
-        double ex = v.Eq[(size_t)i * NJ + j] + sum_tiles_strided(Dga + (size_t)i * dstride + j, nqt, NJ);
-        double es = v.Eq[(size_t)sub * NJ + j] + sum_tiles_strided(Dga + (size_t)sub * dstride + j, nqt, NJ);
-        val = -d * Tx[j] - ex + es;
+        val = -d * Tx[c] - Ea[(size_t)i * NJ + c] + Ea[(size_t)sub * NJ + c];
       } else {
         const int j = c - v.n_z;
-        double ex = v.Eq[(size_t)(v.RZ + i) * NJ + j] + sum_tiles_strided(Dgb + (size_t)i * dstride + j, nqt, NJ);
-        double es = v.Eq[(size_t)(v.RZ + sub) * NJ + j] + sum_tiles_strided(Dgb + (size_t)sub * dstride + j, nqt, NJ);
-        val = -ex + es;
+        val = -Eb[(size_t)i * NJ + j] + Eb[(size_t)sub * NJ + j];
       }
       Jr[c] = val;
     }
   } else {
     const int sub = v.RG - 1;
-    const double* Dha = v.Dp + (size_t)2 * v.RZ * dstride;
+    const double* Eb = v.Eq + (size_t)2 * v.RZ * NJ;
     for (int c = t; c < n; c += blockDim.x) {
       double val;
       if (c < v.n_z) {
-        const int j = c;
-        val = -sum_tiles_strided(Dha + (size_t)i * dstride + j, nqt, NJ)
-              + sum_tiles_strided(Dha + (size_t)sub * dstride + j, nqt, NJ);
+        val = -v.Dgh[(size_t)i * NJ + c] + v.Dgh[(size_t)sub * NJ + c];
       } else {
         const int j = c - v.n_z;
-        val = -d * Tx[j] - v.Eq[(size_t)(2 * v.RZ + i) * NJ + j] + v.Eq[(size_t)(2 * v.RZ + sub) * NJ + j];
+        val = -d * Tx[j] - Eb[(size_t)i * NJ + j] + Eb[(size_t)sub * NJ + j];
       }
       Jr[c] = val;
     }
@@ -499,67 +601,266 @@ __global__ void axpy_kernel(int n, const double* c, double rho, const double* d,
 }
 
 // --------------------------------------------------------------------------
-// FP64 LU with partial pivoting and the triangular solves, one workgroup.
-// Right-looking: per column k the pivot is the first row of largest |A[i][k]|,
-// rows are interchanged whole, multipliers A[i][k] / A[k][k] are stored in
-// place and the trailing block is updated.  M is the matrix storage (LDS or
-// global), row stride ld.
-template <bool IN_LDS>
-__global__ __launch_bounds__(1024) void lu_solve_kernel(int n, const double* __restrict__ Ain,
-                                                        const double* __restrict__ b, double* x,
-                                                        double* __restrict__ Aglob, int* piv,
-                                                        int trans, int* flag) {
-  extern __shared__ double lds[];
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int ld = IN_LDS ? n + 1 : n;
-  double* M = IN_LDS ? lds : Aglob;
-  double* w = IN_LDS ? lds + (size_t)n * ld : lds;  // [n] right-hand side
-  __shared__ int sp;
-  __shared__ int sing;
-  for (int e = t; e < n * n; e += nt) {
-    const int i = e / n, j = e - i * n;
-    M[(size_t)i * ld + j] = Ain[e];
+// FP64 LU with partial pivoting and the triangular solves, one workgroup of
+// four waves, matrix in LDS (or global memory when it does not fit).
+// The matrix is padded to np = 16 ceil(n/16) with an identity block (the
+// padded rows have zeros in the real columns, so they are never chosen as a
+// pivot and the real factors are unchanged) and augmented with the
+// right-hand side as column np.  Blocked right-looking elimination, panel
+// width 16:
+//   panel    wave 0 keeps the panel rows (MR per lane) in registers and
+//            factors it column by column: pivot = first row of largest |a|
+//            (lane maxima, DPP rotate-max within rows, ballot for the first
+//            row), whole-row interchange (registers for the panel's remaining
+//            columns, LDS for the rest), multipliers a / pivot, rank-1 update;
+//   U12      U12 = L11^{-1} A12, one column per thread, in registers;
+//   update   A22 -= L21 U12 by all four waves.
+// The right-hand side column ends as L^{-1} P b; wave 0 back-substitutes by
+// blocks of 16 rows.  The transposed solve (A^T x = b) runs U^T, L^T and P^T
+// with wave 0 after the factorisation.
+constexpr int LU_NB = 16;
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Maximum of v over the wave, returned uniformly (v >= 0 or -1 for none).
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  v = fmax(v, dpp_d<0x121>(v));  // row_ror:1
+  v = fmax(v, dpp_d<0x122>(v));  // row_ror:2
+  v = fmax(v, dpp_d<0x124>(v));  // row_ror:4
+  v = fmax(v, dpp_d<0x128>(v));  // row_ror:8
+  const double r0 = readlane_d(v, 0), r1 = readlane_d(v, 16);
+  const double r2 = readlane_d(v, 32), r3 = readlane_d(v, 48);
+  return fmax(fmax(r0, r1), fmax(r2, r3));
+}
+
+// One panel column at compile-time register offset O: P[m][O] is column kc.
+// Register rows never move: lpos[m] is the row position a register row holds
+// after the interchanges so far (rows interchange logically in registers and
+// physically in LDS, so the stored factors keep whole-row-interchange order).
+template <int MR, int O>
+__device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], double* M, int ld, int ncol,
+                                       int lane, int k0, int kc, int* spiv, int& sing) {
+  double cand[MR];
+  double lmax = -1.0;
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    cand[m] = lpos[m] >= kc ? fabs(P[m][O]) : -1.0;  // rows not yet used as pivots
+    lmax = fmax(lmax, cand[m]);
   }
-  for (int i = t; i < n; i += nt) w[i] = b[i];
-  if (t == 0) sing = 0;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (t < 64) {
-      double best = -1.0;
-      int bi = n;
-      for (int i = k + t; i < n; i += 64) {
-        const double a = fabs(M[(size_t)i * ld + k]);
-        if (a > best) { best = a; bi = i; }
+  const double gmax = wave_max_nonneg(lmax);
+  if (!(gmax > 0.0) || isinf(gmax)) { sing = 1; return; }
+  // first row position (after interchanges) holding the maximum
+  int best_pos = 1 << 30;
+#pragma unroll
+  for (int m = 0; m < MR; ++m)
+    if (cand[m] == gmax) best_pos = min(best_pos, lpos[m]);
+  // wave minimum of best_pos (integers, DPP rotate-min within rows + lane reads)
+  int bp = best_pos;
+  bp = min(bp, __builtin_amdgcn_update_dpp(0, bp, 0x121, 0xf, 0xf, false));
+  bp = min(bp, __builtin_amdgcn_update_dpp(0, bp, 0x122, 0xf, 0xf, false));
+  bp = min(bp, __builtin_amdgcn_update_dpp(0, bp, 0x124, 0xf, 0xf, false));
+  bp = min(bp, __builtin_amdgcn_update_dpp(0, bp, 0x128, 0xf, 0xf, false));
+  const int p = min(min(__builtin_amdgcn_readlane(bp, 0), __builtin_amdgcn_readlane(bp, 16)),
+                    min(__builtin_amdgcn_readlane(bp, 32), __builtin_amdgcn_readlane(bp, 48)));
+  if (lane == 0) spiv[kc] = p;
+  // physical register row holding position p
+  unsigned long long mk[MR];
+  int lp = 0, mp = 0;
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    mk[m] = __ballot(lpos[m] == p);
+    if (mk[m]) { lp = (int)__builtin_ctzll(mk[m]); mp = m; }
+  }
+  // the pivot row's panel entries [kc, k0 + LU_NB) are a row of U: the lane
+  // holding it writes them to row kc (those columns of row kc are not read
+  // again from memory before the panel is written back), and every lane reads
+  // them back below, which is also the broadcast
+  if (lane == lp) {
+#pragma unroll
+    for (int cc = O; cc < LU_NB; ++cc) {
+      double sel = P[0][cc];
+#pragma unroll
+      for (int m = 1; m < MR; ++m) if (mp == m) sel = P[m][cc];
+      M[(size_t)kc * ld + k0 + cc] = sel;
+    }
+  }
+  if (p != kc) {
+    // logical interchange of the register rows
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      if (lpos[m] == kc) lpos[m] = p;
+      else if (lpos[m] == p) lpos[m] = kc;
+    }
+    // physical interchange of the two rows outside the columns in registers
+    const int jhi = k0 + LU_NB;
+    double a[3], bb[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int j = lane + 64 * u;
+      const bool ok = j < ncol && (j < kc || j >= jhi);
+      a[u] = ok ? M[(size_t)kc * ld + j] : 0.0;
+      bb[u] = ok ? M[(size_t)p * ld + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int j = lane + 64 * u;
+      if (j < ncol && (j < kc || j >= jhi)) {
+        M[(size_t)kc * ld + j] = bb[u];
+        M[(size_t)p * ld + j] = a[u];
+      }
+    }
+    for (int j = lane + 192; j < ncol; j += 64) {  // ncol > 192 (n > 191)
+      if (j < kc || j >= jhi) {
+        const double x0 = M[(size_t)kc * ld + j];
+        const double x1 = M[(size_t)p * ld + j];
+        M[(size_t)kc * ld + j] = x1;
+        M[(size_t)p * ld + j] = x0;
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  double rp[LU_NB];
+#pragma unroll
+  for (int cc = O; cc < LU_NB; ++cc) rp[cc] = M[(size_t)kc * ld + k0 + cc];
+  const double dinv_src = rp[O];
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    if (lpos[m] > kc) {
+      const double l = P[m][O] / dinv_src;
+      M[(size_t)lpos[m] * ld + kc] = l;
+#pragma unroll
+      for (int cc = O + 1; cc < LU_NB; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
+    }
+  }
+}
+
+template <bool IN_LDS, int MR>
+__global__ __launch_bounds__(256) void lu_solve_kernel(int n, const double* __restrict__ Ain,
+                                                       const double* __restrict__ b, double* x,
+                                                       double* __restrict__ Aglob, int* piv,
+                                                       int trans, int* flag) {
+  extern __shared__ double lds[];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
+  const int ld = np + 1;  // column np holds the right-hand side (non-transposed solve)
+  const int ncol = np + 1;
+  double* M = IN_LDS ? lds : Aglob;
+  __shared__ int spiv[256];
+  __shared__ int sing;
+  __shared__ double wsv[256];
+  // load [A | b] padded with an identity block; eight rows per wave in flight
+  for (int i0 = wave * 8; i0 < np; i0 += 32) {
+    for (int j = lane; j < ncol; j += 64) {
+      double v_[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u;
+        if (j == np) v_[u] = (i < n && !trans) ? b[i] : 0.0;
+        else if (i < n && j < n) v_[u] = Ain[(size_t)i * n + j];
+        else v_[u] = (i == j) ? 1.0 : 0.0;
       }
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < np) M[(size_t)(i0 + u) * ld + j] = v_[u];
+    }
+  }
+  if (t == 0) sing = 0;
+  __syncthreads();
+
+  for (int k0 = 0; k0 < np; k0 += LU_NB) {
+    if (wave == 0) {
+      double P[MR][LU_NB];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int r = k0 + lane + 64 * m;
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) P[m][c] = r < np ? M[(size_t)r * ld + k0 + c] : 0.0;
       }
-      if (t == 0) {
-        sp = bi;
-        piv[k] = bi;
-        if (!(best > 0.0) || isinf(best)) sing = 1;
+      int sg = 0;
+      int lpos[MR];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int r = k0 + lane + 64 * m;
+        lpos[m] = r < np ? r : -1;  // -1: no row (never a candidate, never updated)
       }
+      // four groups of four columns: compile-time offsets inside a group,
+      // the group's columns shift to the front afterwards
+      for (int g = 0; g < LU_NB; g += 4) {
+        lu_col<MR, 0>(P, lpos, M, ld, ncol, lane, k0, k0 + g + 0, spiv, sg);
+        if (sg) break;
+        lu_col<MR, 1>(P, lpos, M, ld, ncol, lane, k0, k0 + g + 1, spiv, sg);
+        if (sg) break;
+        lu_col<MR, 2>(P, lpos, M, ld, ncol, lane, k0, k0 + g + 2, spiv, sg);
+        if (sg) break;
+        lu_col<MR, 3>(P, lpos, M, ld, ncol, lane, k0, k0 + g + 3, spiv, sg);
+        if (sg) break;
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+#pragma unroll
+          for (int cc = 0; cc < LU_NB - 4; ++cc) P[m][cc] = P[m][cc + 4];
+        }
+      }
+      if (sg && lane == 0) sing = 1;
     }
     __syncthreads();
     if (sing) break;
-    const int p = sp;
-    if (p != k)
-      for (int j = t; j < n; j += nt) {
-        const double tmp = M[(size_t)k * ld + j];
-        M[(size_t)k * ld + j] = M[(size_t)p * ld + j];
-        M[(size_t)p * ld + j] = tmp;
+    const int j0 = k0 + LU_NB;
+    // U12 = L11^{-1} A12: one column per thread, in registers
+    for (int j = j0 + t; j < ncol; j += 256) {
+      double u[LU_NB];
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) u[c] = M[(size_t)(k0 + c) * ld + j];
+#pragma unroll
+      for (int c = 1; c < LU_NB; ++c) {
+        const double* Lr = M + (size_t)(k0 + c) * ld + k0;
+        double s_ = u[c];
+#pragma unroll
+        for (int cc = 0; cc < c; ++cc) s_ = fma(-Lr[cc], u[cc], s_);
+        u[c] = s_;
       }
+#pragma unroll
+      for (int c = 1; c < LU_NB; ++c) M[(size_t)(k0 + c) * ld + j] = u[c];
+    }
     __syncthreads();
-    const double dk = M[(size_t)k * ld + k];
-    for (int i = k + 1 + t; i < n; i += nt) M[(size_t)i * ld + k] = M[(size_t)i * ld + k] / dk;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int e = t; e < m * m; e += nt) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      M[(size_t)i * ld + j] -= M[(size_t)i * ld + k] * M[(size_t)k * ld + j];
+    // trailing update A22 -= L21 U12: lane -> column, wave -> pairs of rows
+    for (int jj = j0 + lane; jj < ncol; jj += 64) {
+      double u[LU_NB];
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) u[c] = M[(size_t)(k0 + c) * ld + jj];
+      int i = j0 + 2 * wave;
+      for (; i + 1 < np; i += 8) {
+        const double* L0 = M + (size_t)i * ld + k0;
+        const double* L1 = L0 + ld;
+        double s0 = M[(size_t)i * ld + jj], s1 = M[(size_t)(i + 1) * ld + jj];
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) {
+          s0 = fma(-L0[c], u[c], s0);
+          s1 = fma(-L1[c], u[c], s1);
+        }
+        M[(size_t)i * ld + jj] = s0;
+        M[(size_t)(i + 1) * ld + jj] = s1;
+      }
+      if (i < np) {
+        const double* L0 = M + (size_t)i * ld + k0;
+        double s0 = M[(size_t)i * ld + jj];
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) s0 = fma(-L0[c], u[c], s0);
+        M[(size_t)i * ld + jj] = s0;
+      }
     }
     __syncthreads();
   }
@@ -567,47 +868,183 @@ __global__ __launch_bounds__(1024) void lu_solve_kernel(int n, const double* __r
     if (t == 0) flag[0] = 4;
     return;
   }
+  for (int i = t; i < n; i += 256) piv[i] = spiv[i];
+  if (wave != 0) return;
+  // wave 0: w distributed as rows lane + 64 m
+  double w[MR];
   if (!trans) {
-    if (t == 0)
-      for (int k = 0; k < n; ++k) {
-        const int pk = piv[k];
-        const double tmp = w[k]; w[k] = w[pk]; w[pk] = tmp;
-      }
-    __syncthreads();
-    for (int i = 0; i < n; ++i) {  // L y = P b (unit lower)
-      const double wi = w[i];
-      for (int r = i + 1 + t; r < n; r += nt) w[r] -= M[(size_t)r * ld + i] * wi;
-      __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      const int r = lane + 64 * m;
+      w[m] = r < np ? M[(size_t)r * ld + np] : 0.0;  // = L^{-1} P b
     }
-    for (int i = n - 1; i >= 0; --i) {  // U x = y
-      if (t == 0) w[i] = w[i] / M[(size_t)i * ld + i];
-      __syncthreads();
-      const double wi = w[i];
-      for (int r = t; r < i; r += nt) w[r] -= M[(size_t)r * ld + i] * wi;
-      __syncthreads();
+    // U x = y by blocks of 16 rows from the bottom: solve the diagonal block
+    // (values broadcast by lane reads), then update the rows above
+    for (int i1 = np; i1 > 0; i1 -= LU_NB) {
+      const int i0 = i1 - LU_NB;
+      const int mi = i0 >> 6;
+      double xb[LU_NB], dg[LU_NB], ub[MR][LU_NB];
+#pragma unroll
+      for (int cc = 0; cc < LU_NB; ++cc) dg[cc] = M[(size_t)(i0 + cc) * ld + i0 + cc];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int r = lane + 64 * m;
+        const bool in = r >= i0 && r < i1;
+#pragma unroll
+        for (int cc = 0; cc < LU_NB; ++cc) ub[m][cc] = in ? M[(size_t)r * ld + i0 + cc] : 0.0;
+      }
+#pragma unroll
+      for (int cc = LU_NB - 1; cc >= 0; --cc) {
+        const int i = i0 + cc;
+        double sel = w[0];
+#pragma unroll
+        for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
+        const double xi = readlane_d(sel, i & 63) / dg[cc];
+        xb[cc] = xi;
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+          const int r = lane + 64 * m;
+          if (r == i) w[m] = xi;
+          else if (r >= i0 && r < i) w[m] = fma(-ub[m][cc], xi, w[m]);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int r = lane + 64 * m;
+        if (r < i0) {
+          const double* Ur = M + (size_t)r * ld + i0;
+          double s_ = w[m];
+#pragma unroll
+          for (int cc = 0; cc < LU_NB; ++cc) s_ = fma(-Ur[cc], xb[cc], s_);
+          w[m] = s_;
+        }
+      }
     }
   } else {
-    for (int i = 0; i < n; ++i) {  // U^T y = b
-      if (t == 0) w[i] = w[i] / M[(size_t)i * ld + i];
-      __syncthreads();
-      const double wi = w[i];
-      for (int r = i + 1 + t; r < n; r += nt) w[r] -= M[(size_t)i * ld + r] * wi;
-      __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      const int r = lane + 64 * m;
+      w[m] = r < n ? b[r] : 0.0;
     }
-    for (int i = n - 1; i >= 0; --i) {  // L^T z = y
-      const double wi = w[i];
-      for (int r = t; r < i; r += nt) w[r] -= M[(size_t)i * ld + r] * wi;
-      __syncthreads();
-    }
-    if (t == 0)
-      for (int k = n - 1; k >= 0; --k) {
-        const int pk = piv[k];
-        const double tmp = w[k]; w[k] = w[pk]; w[pk] = tmp;
+    for (int i = 0; i < np; ++i) {  // U^T y = b
+      const int li = i & 63, mi = i >> 6;
+      double sel = w[0];
+#pragma unroll
+      for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
+      const double yi = readlane_d(sel, li) / M[(size_t)i * ld + i];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int r = lane + 64 * m;
+        if (r == i) w[m] = yi;
+        else if (r > i && r < np) w[m] = fma(-M[(size_t)i * ld + r], yi, w[m]);
       }
+    }
+    for (int i = np - 1; i >= 0; --i) {  // L^T z = y (unit diagonal)
+      const int li = i & 63, mi = i >> 6;
+      double sel = w[0];
+#pragma unroll
+      for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
+      const double zi = readlane_d(sel, li);
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int r = lane + 64 * m;
+        if (r < i) w[m] = fma(-M[(size_t)i * ld + r], zi, w[m]);
+      }
+    }
+    // x = P^T z: undo the interchanges in reverse order (staged in LDS)
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      const int r = lane + 64 * m;
+      if (r < np) wsv[r] = w[m];
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0)
+      for (int k = np - 1; k >= 0; --k) {
+        const int pk = spiv[k];
+        const double tmp = wsv[k]; wsv[k] = wsv[pk]; wsv[pk] = tmp;
+      }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      const int r = lane + 64 * m;
+      if (r < np) w[m] = wsv[r];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const int r = lane + 64 * m;
+    if (r < n) x[r] = w[m];
+  }
+  if (lane == 0) flag[0] = 0;
+}
+
+// --------------------------------------------------------------------------
+// Vector-Jacobian products.  With row weights rw = -u_i on the collocation
+// rows and rw = sum_i u_i (over the same kind) on the subtraction rows,
+//   u^T F = sum_rows rw Pi + sum_i u_i (direct_i - parameter)
+// so the weighted point kernel plus the contraction give u^T dF/dc, and the
+// weighted alpha sums give u^T dF/d alpha.
+__global__ __launch_bounds__(256) void row_weights_kernel(Views v, const double* __restrict__ u) {
+  __shared__ double red[2][256];
+  const int t = threadIdx.x;
+  double sz = 0.0, sg = 0.0;
+  for (int i = t; i < v.n_z; i += 256) sz += u[i];
+  for (int i = t; i < v.n_g; i += 256) sg += u[v.n_z + i];
+  red[0][t] = sz;
+  red[1][t] = sg;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) { red[0][t] += red[0][t + o]; red[1][t] += red[1][t + o]; }
     __syncthreads();
   }
-  for (int i = t; i < n; i += nt) x[i] = w[i];
-  if (t == 0) flag[0] = 0;
+  for (int i = t; i < v.n_z; i += 256) v.rw[i] = -u[i];
+  for (int i = t; i < v.n_g; i += 256) v.rw[v.RZ + i] = -u[v.n_z + i];
+  if (t == 0) {
+    v.rw[v.RZ - 1] = red[0][0];
+    v.rw[v.RZ + v.RG - 1] = red[1][0];
+  }
+}
+
+// u^T dF/dc (optional) and u^T dF/dtheta, theta = (alpha_mu, g0_inv, z_lambda_inv).
+__global__ __launch_bounds__(256) void vjp_reduce_kernel(Views v, const double* __restrict__ u,
+                                                         double* uJ, double* uth) {
+  const int t = threadIdx.x;
+  const int NJ = v.NJ;
+  if (uJ) {
+    for (int c = t; c < v.n; c += 256) {
+      double s_ = 0.0;
+      if (c < v.n_z) {
+        const int j = c;
+        for (int r = 0; r < v.RZ; ++r) s_ += v.Eq[(size_t)r * NJ + j];
+        for (int r = 0; r < v.RG; ++r) s_ += v.Dgh[(size_t)r * NJ + j];
+        for (int i = 0; i < v.n_z; ++i) s_ -= u[i] * exp(-v.lnX[i]) * v.Text[(size_t)i * NJ + j];
+      } else {
+        const int j = c - v.n_z;
+        for (int r = 0; r < v.RZ; ++r) s_ += v.Eq[(size_t)(v.RZ + r) * NJ + j];
+        for (int r = 0; r < v.RG; ++r) s_ += v.Eq[(size_t)(2 * v.RZ + r) * NJ + j];
+        for (int i = 0; i < v.n_g; ++i)
+          s_ -= u[v.n_z + i] * exp(-v.lnX[v.n_z + i]) * v.Text[(size_t)(v.n_z + i) * NJ + j];
+      }
+      uJ[c] = s_;
+    }
+  }
+  if (uth && t == 0) {
+    const int nt = v.nqt * v.KS;
+    double s_ = 0.0, c_ = 0.0;
+    for (int r = 0; r < v.RZ + v.RG; ++r)
+      for (int k = 0; k < nt; ++k) {
+        two_sum_add(s_, c_, v.Pip[2 * ((size_t)r * nt + k)]);
+        c_ += v.Pip[2 * ((size_t)r * nt + k) + 1];
+      }
+    double sz = 0.0, sg = 0.0;
+    for (int i = 0; i < v.n_z; ++i) sz += u[i];
+    for (int i = 0; i < v.n_g; ++i) sg += u[v.n_z + i];
+    uth[0] = s_ + c_;   // d/d alpha: through the self-energies only
+    uth[1] = -sg;       // dF^G/d g0_inv = -1
+    uth[2] = -sz;       // dF^Z/d z_lambda_inv = -1
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -618,35 +1055,52 @@ hipError_t launch_dressing(const Views& v, const Phys& ph, const double* c, hipS
   return hipGetLastError();
 }
 
-template <int NJ, bool JAC>
+template <int NJ, int MODE>
 static hipError_t points_nj(const Views& v, const Phys& ph, hipStream_t st, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL((point_kernel<GLUON, NJ, JAC>), dim3(v.RZ * v.nqt), dim3(256), 0, st, v, ph);
+  hipLaunchKernelGGL((point_kernel<GLUON, NJ, MODE>), dim3(v.RZ * v.nqt * v.KS), dim3(256), 0, st, v, ph);
   if (ev) (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((point_kernel<GHOST, NJ, JAC>), dim3(v.RG * v.nqt), dim3(256), 0, st, v, ph);
+  hipLaunchKernelGGL((point_kernel<GHOST, NJ, MODE>), dim3(v.RG * v.nqt * v.KS), dim3(256), 0, st, v, ph);
   if (ev) (void)hipEventRecord(ev[2], st);
   return hipGetLastError();
 }
 
-template <bool JAC>
+template <int MODE>
 static hipError_t points_dispatch(const Views& v, const Phys& ph, hipStream_t st, hipEvent_t* ev) {
   switch (v.NJ) {
-    case 16: return points_nj<16, JAC>(v, ph, st, ev);
-    case 32: return points_nj<32, JAC>(v, ph, st, ev);
-    case 48: return points_nj<48, JAC>(v, ph, st, ev);
-    case 64: return points_nj<64, JAC>(v, ph, st, ev);
-    case 96: return points_nj<96, JAC>(v, ph, st, ev);
-    case 128: return points_nj<128, JAC>(v, ph, st, ev);
+    case 16: return points_nj<16, MODE>(v, ph, st, ev);
+    case 32: return points_nj<32, MODE>(v, ph, st, ev);
+    case 48: return points_nj<48, MODE>(v, ph, st, ev);
+    case 64: return points_nj<64, MODE>(v, ph, st, ev);
+    case 96: return points_nj<96, MODE>(v, ph, st, ev);
+    case 128: return points_nj<128, MODE>(v, ph, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_points(const Views& v, const Phys& ph, bool jacobian, hipStream_t st, hipEvent_t* ev) {
-  return jacobian ? points_dispatch<true>(v, ph, st, ev) : points_dispatch<false>(v, ph, st, ev);
+hipError_t launch_points(const Views& v, const Phys& ph, int mode, hipStream_t st, hipEvent_t* ev) {
+  switch (mode) {
+    case MODE_RES: return points_dispatch<MODE_RES>(v, ph, st, ev);
+    case MODE_JAC: return points_dispatch<MODE_JAC>(v, ph, st, ev);
+    case MODE_VJP: return points_dispatch<MODE_VJP>(v, ph, st, ev);
+    case MODE_VTH: return points_dispatch<MODE_VTH>(v, ph, st, ev);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_contract(const Views& v, hipStream_t st) {
-  hipLaunchKernelGGL(contract_kernel, dim3(v.Rbp / 16, v.NJ / 16), dim3(256), 0, st, v);
+  const int gh_blocks = (v.RG + 15) / 16;
+  hipLaunchKernelGGL(contract_kernel, dim3(v.Rbp / 16 + gh_blocks, v.NJ / 16), dim3(256), 0, st, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_weights(const Views& v, const double* u, hipStream_t st) {
+  hipLaunchKernelGGL(row_weights_kernel, dim3(1), dim3(256), 0, st, v, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_reduce(const Views& v, const double* u, double* uJ, double* uth, hipStream_t st) {
+  hipLaunchKernelGGL(vjp_reduce_kernel, dim3(1), dim3(256), 0, st, v, u, uJ, uth);
   return hipGetLastError();
 }
 
@@ -671,11 +1125,19 @@ hipError_t launch_axpy(int n, const double* c, double rho, const double* d, doub
   return hipGetLastError();
 }
 
+template <bool IN_LDS, int MR>
+static void set_lu_lds(int bytes) {
+  (void)hipFuncSetAttribute((const void*)lu_solve_kernel<IN_LDS, MR>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x, int trans,
                            hipStream_t st) {
   const int n = v.n;
-  const size_t lds_bytes = ((size_t)n * (n + 1) + n) * sizeof(double);
-  // largest dynamic LDS a workgroup may use on this device (160 KiB on gfx950)
+  const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
+  // factors of [A | b], padded, in dynamic LDS when they fit
+  const size_t lds_bytes = (size_t)np * (np + 1) * sizeof(double);
+  const size_t static_bytes = 256 * 4 + 256 * 8 + 64;
   static int max_lds = -1;
   if (max_lds < 0) {
     int dev = 0, val = 0;
@@ -683,17 +1145,25 @@ hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, dou
         hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
       val = 64 * 1024;
     max_lds = val;
-    if (max_lds > 64 * 1024 &&
-        hipFuncSetAttribute((const void*)lu_solve_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            max_lds - 1024) != hipSuccess)
-      max_lds = 64 * 1024;
+    const int dyn = max_lds - (int)static_bytes;
+    set_lu_lds<true, 2>(dyn);
+    set_lu_lds<true, 4>(dyn);
   }
-  if (lds_bytes + 1024 <= (size_t)max_lds) {
-    hipLaunchKernelGGL(lu_solve_kernel<true>, dim3(1), dim3(1024), lds_bytes, st, n, A, b, x, v.LU, v.piv,
-                       trans, v.flag);
+  const bool fits = lds_bytes + static_bytes <= (size_t)max_lds;
+  if (np <= 128) {
+    if (fits)
+      hipLaunchKernelGGL((lu_solve_kernel<true, 2>), dim3(1), dim3(256), lds_bytes, st, n, A, b, x, v.LU, v.piv,
+                         trans, v.flag);
+    else
+      hipLaunchKernelGGL((lu_solve_kernel<false, 2>), dim3(1), dim3(256), 0, st, n, A, b, x, v.LU, v.piv, trans,
+                         v.flag);
   } else {
-    hipLaunchKernelGGL(lu_solve_kernel<false>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, n, A, b,
-                       x, v.LU, v.piv, trans, v.flag);
+    if (fits)
+      hipLaunchKernelGGL((lu_solve_kernel<true, 4>), dim3(1), dim3(256), lds_bytes, st, n, A, b, x, v.LU, v.piv,
+                         trans, v.flag);
+    else
+      hipLaunchKernelGGL((lu_solve_kernel<false, 4>), dim3(1), dim3(256), 0, st, n, A, b, x, v.LU, v.piv, trans,
+                         v.flag);
   }
   return hipGetLastError();
 }

@@ -25,7 +25,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "HIP device error", 3: "workspace t
 EXPORTS = [
     "dse_params_default", "dse_workspace_bytes", "dse_init", "dse_destroy", "dse_start_guess",
     "dse_residual", "dse_jacobian", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
-    "dse_last_error", "dse_sizes", "dse_set_timing", "dse_read_timings",
+    "dse_last_error", "dse_sizes", "dse_set_timing", "dse_read_timings", "dse_vjp",
+    "dse_set_physics",
 ]
 
 
@@ -86,6 +87,8 @@ def load():
                                     C.POINTER(C.c_int32)]),
             "dse_set_timing": (C.c_int, [vp, C.c_int32]),
             "dse_read_timings": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+            "dse_vjp": (C.c_int, [vp, vp, vp, vp, vp]),
+            "dse_set_physics": (C.c_int, [vp, C.c_double, C.c_double, C.c_double]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -229,6 +232,23 @@ class Solver:
                             relax_hist=list(rep.relax_hist[: rep.iters]),
                             n_jacobians=rep.n_jacobians, n_residuals=rep.n_residuals,
                             t_total_ms=rep.t_total_ms)
+
+    def vjp(self, c, u, with_c: bool = True):
+        """u^T dF/dc (or None) and u^T dF/d(alpha_mu, g0_inv, z_lambda_inv)."""
+        c = self._vec(c)
+        u = self._vec(u)
+        uJ = self._vec() if with_c else None
+        ut = torch.empty(3, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_vjp(self.h, _ptr(c), _ptr(u), _ptr(uJ), _ptr(ut)))
+        return uJ, ut
+
+    def set_physics(self, alpha_mu=None, g0_inv=None, z_lambda_inv=None):
+        a = self.p.alpha_mu if alpha_mu is None else float(alpha_mu)
+        g = self.p.g0_inv if g0_inv is None else float(g0_inv)
+        z = self.p.z_lambda_inv if z_lambda_inv is None else float(z_lambda_inv)
+        self._check(self.lib.dse_set_physics(self.h, a, g, z))
+        self.p.alpha_mu, self.p.g0_inv, self.p.z_lambda_inv = a, g, z
 
     def set_timing(self, on: bool = True):
         self._check(self.lib.dse_set_timing(self.h, 1 if on else 0))
