@@ -88,12 +88,13 @@ typedef struct {
 } dse_params;
 
 /* Newton options (Sec. 3 under-relaxed Newton-Raphson).  The relaxation rho
- * starts at 1 and is halved, at most max_halvings times, while the scaled
- * residual of the trial point is not below the current one.  Convergence:
- * scaled residual max_r |F_r| / S_r < tol, where S_r is the magnitude of the
- * terms that cancel in F_r (direct term, parameter, and the sums of
- * |integrand| at x_r and at the subtraction point).  Then extra_iters full
- * steps follow, stopping early once rho ||Delta||_inf < step_tol. */
+ * starts at 1 and is halved, at most max_halvings times, while the Euclidean
+ * norm of the scaled residual, (sum_r (F_r / S_r)^2)^{1/2}, at the trial point
+ * is not below the current one.  Convergence: scaled residual
+ * max_r |F_r| / S_r < tol, where S_r is the magnitude of the terms that
+ * cancel in F_r (direct term, parameter, and the sums of |integrand| at x_r
+ * and at the subtraction point).  Then extra_iters full steps follow,
+ * stopping early once rho ||Delta||_inf < step_tol. */
 typedef struct {
   double tol;
   int32_t max_iter;
@@ -196,6 +197,70 @@ dse_status dse_sizes(const dse_ctx* ctx, int32_t* n, int32_t* n_radial, int32_t*
  * dse_set_timing() resets the averages. */
 dse_status dse_set_timing(dse_ctx* ctx, int32_t on);
 dse_status dse_read_timings(dse_ctx* ctx, double* ms5, int32_t* count);
+
+/* ------------------------------------------------------------------------
+ * Batched family.  `count` independent problems, each with its own
+ * dse_params (orders, grids and physics may differ: e.g. the family of
+ * decoupling solutions labelled by G(0), Sec. 2), assembled and solved
+ * together: every stage is one launch for the whole family, and the
+ * point work is one queue of (problem, row, radial tile, angular slice)
+ * items, largest first.
+ *
+ * Packed layouts: the unknowns of problem b occupy c[off_c[b] .. off_c[b+1])
+ * of one vector (same order as a single problem), and its Newton matrix
+ * J[off_J[b] .. off_J[b+1]) (n_b x n_b, row-major); dse_batch_offsets gives
+ * both (count + 1 entries each, off[0] = 0).
+ * Ownership, stream and error rules are those of the single-problem calls;
+ * the workspace of dse_batch_workspace_bytes() holds every problem's tables
+ * and buffers and the work queue.
+ * ------------------------------------------------------------------------ */
+typedef struct dse_batch dse_batch; /* opaque */
+
+/* Result of dse_batch_autotune: the launch chosen and every candidate timed
+ * (device ms of one Newton-matrix assembly of the whole family). */
+typedef struct {
+  int32_t slices;             /* angular slices per (row, radial tile)                */
+  int32_t persistent_blocks;  /* 0: one workgroup per queue item; > 0: that many
+                                 persistent workgroups taking items from the queue    */
+  int32_t order;              /* 1: queue ordered largest item first; 0: problem order */
+  int32_t n_candidates;
+  double best_ms;
+  int32_t cand_slices[32];
+  int32_t cand_blocks[32];
+  int32_t cand_order[32];
+  double cand_ms[32];
+} dse_batch_tuning;
+
+size_t dse_batch_workspace_bytes(const dse_params* p, int32_t count);
+/* p[count]: validated like dse_init (DSE_E_INVALID names the problem). */
+dse_status dse_batch_init(const dse_params* p, int32_t count, void* d_workspace, size_t ws_bytes,
+                          void* hip_stream, dse_batch** out);
+dse_status dse_batch_destroy(dse_batch* b);
+const char* dse_batch_last_error(const dse_batch* b);
+/* h_off_c, h_off_J: host arrays of count + 1 entries (either may be NULL). */
+dse_status dse_batch_offsets(const dse_batch* b, int64_t* h_off_c, int64_t* h_off_J);
+/* Start guesses (as dse_start_guess) of every problem into the packed d_c. */
+dse_status dse_batch_start_guess(dse_batch* b, double* d_c);
+/* Newton matrices and residuals of every problem at the packed d_c, into the
+ * packed d_J and d_F (nullable).  Synchronises. */
+dse_status dse_batch_jacobian(dse_batch* b, const double* d_c, double* d_J, double* d_F);
+/* Every problem solved by the iteration of dse_newton_solve, step for step,
+ * from the packed d_c (overwritten by the last iterates).  h_reports: host
+ * array of count reports (nullable).  Returns DSE_OK when every problem
+ * converged, else the status of the first problem that did not (its report
+ * says which). */
+dse_status dse_batch_newton_solve(dse_batch* b, double* d_c, const dse_newton_opts* opts,
+                                  dse_newton_report* h_reports);
+/* Times every launch candidate (slices 1, 2, 4 as the angular grid allows;
+ * one workgroup per item or persistent workgroups filling the device; queue
+ * largest first or in problem order) on the family's Newton-matrix assembly at
+ * d_c and keeps the fastest.  h_out nullable. */
+dse_status dse_batch_autotune(dse_batch* b, const double* d_c, dse_batch_tuning* h_out);
+/* Sets (or reads back) the launch explicitly; slices a power of two within
+ * what the angular grid allows. */
+dse_status dse_batch_set_launch(dse_batch* b, int32_t slices, int32_t persistent_blocks, int32_t order);
+dse_status dse_batch_get_launch(const dse_batch* b, int32_t* slices, int32_t* persistent_blocks,
+                                int32_t* order);
 
 #ifdef __cplusplus
 }

@@ -685,7 +685,8 @@ static double norminf(const double* v, int n) {
   for (int i = 0; i < n; ++i) if (fabs(v[i]) > s) s = fabs(v[i]);
   return s;
 }
-/* Scaled residual max_r |F_r| / S_r: F relative to the size of its terms. */
+/* Scaled residual max_r |F_r| / S_r: F relative to the size of its terms
+ * (the convergence test). */
 static double merit(const double* F, const double* S, int n) {
   double m = 0.0;
   for (int i = 0; i < n; ++i) {
@@ -693,6 +694,17 @@ static double merit(const double* F, const double* S, int n) {
     if (!(v <= m)) m = v; /* propagates NaN */
   }
   return m;
+}
+/* Euclidean norm of the scaled residual, (sum_r (F_r / S_r)^2)^{1/2}: the
+ * function the relaxation must decrease (smooth, unlike the maximum, whose
+ * plateaus stall the halving rule far from the root). */
+static double merit2(const double* F, const double* S, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double v = S[i] > 0.0 ? F[i] / S[i] : F[i];
+    s += v * v;
+  }
+  return sqrt(s);
 }
 
 /* Sec. 3: c^{n+1} = c^n - rho Delta^{n+1} with J Delta = F.  rho starts at 1
@@ -713,6 +725,7 @@ int dse_ref_newton(const dse_ref_params* p, double* c, const dse_ref_newton_opts
   memset(rep, 0, sizeof(*rep));
   int st = resid_scale(p, c, F, S);
   double f = st ? INFINITY : merit(F, S, n);
+  double f2 = st ? INFINITY : merit2(F, S, n);
   rep->fnorm_hist[0] = f;
   int it = 0, extra = 0;
   if (st) goto done;
@@ -726,13 +739,15 @@ int dse_ref_newton(const dse_ref_params* p, double* c, const dse_ref_newton_opts
     if (st) break;
     st = dse_ref_lu_solve(n, J, F, d, 0);
     if (st) break;
-    double rho = 1.0, ft = INFINITY;
+    double rho = 1.0, ft = INFINITY, ft2 = INFINITY;
     int converged = f < o->tol;
     for (int h = 0;; ++h) {
       for (int i = 0; i < n; ++i) ct[i] = c[i] - rho * d[i];
       int s2 = resid_scale(p, ct, Ft, St);
       ft = s2 ? INFINITY : merit(Ft, St, n);
-      if (converged || ft < f || h >= o->max_halvings) break;
+      ft2 = s2 ? INFINITY : merit2(Ft, St, n);
+      if (!isfinite(ft)) ft2 = INFINITY;
+      if (converged || ft2 < f2 || h >= o->max_halvings) break;
       rho *= 0.5;
     }
     if (!isfinite(ft)) { st = 6; break; }
@@ -740,6 +755,7 @@ int dse_ref_newton(const dse_ref_params* p, double* c, const dse_ref_newton_opts
     memcpy(F, Ft, sizeof(double) * n);
     memcpy(S, St, sizeof(double) * n);
     f = ft;
+    f2 = ft2;
     ++it;
     if (it < 128) { rep->fnorm_hist[it] = f; rep->relax_hist[it - 1] = rho; }
     if (converged && rho * norminf(d, n) < o->step_tol) { st = 0; break; }

@@ -36,9 +36,7 @@ struct dse_ctx {
 
 static char g_init_err[512];
 
-namespace {
-
-constexpr double kPi = 3.14159265358979323846264338327950288;
+namespace dse {
 
 void set_err(char* buf, const char* fmt, ...) {
   va_list ap;
@@ -46,6 +44,13 @@ void set_err(char* buf, const char* fmt, ...) {
   vsnprintf(buf, 512, fmt, ap);
   va_end(ap);
 }
+
+}  // namespace dse
+
+namespace {
+
+using dse::kPi;
+using dse::set_err;
 
 #define HIP_TRY(ctx, expr)                                                          \
   do {                                                                              \
@@ -55,6 +60,10 @@ void set_err(char* buf, const char* fmt, ...) {
       return DSE_E_DEVICE;                                                          \
     }                                                                               \
   } while (0)
+
+}  // namespace
+
+namespace dse {
 
 // Gauss-Legendre nodes (ascending) and weights on [-1, 1]: Newton's method on
 // the Legendre polynomial evaluated by Bonnet's recursion, started from the
@@ -155,8 +164,8 @@ dse_status validate(const dse_params* p, char* err) {
   return DSE_OK;
 }
 
-dse::Phys make_phys(const dse_params& p) {
-  dse::Phys ph;
+Phys make_phys(const dse_params& p) {
+  Phys ph;
   ph.C = p.alpha_mu * p.n_c / (2.0 * kPi * kPi);
   ph.omega = 11.0 * p.n_c * p.alpha_mu / (12.0 * kPi);
   ph.e1 = -2.0 - 6.0 * p.delta;
@@ -175,12 +184,10 @@ dse::Phys make_phys(const dse_params& p) {
   return ph;
 }
 
-}  // namespace
-
-namespace dse {
-
-// Carves the workspace; with base == nullptr only sizes it.
-size_t layout(const dse_params& p, Views* v, char* base) {
+// Carves the workspace; with base == nullptr only sizes it.  ks > 0 fixes the
+// number of angular slices (the buffers are sized for it); 0 picks it from the
+// problem size.
+size_t layout(const dse_params& p, Views* v, char* base, int ks) {
   Views t{};
   t.n_z = p.n_z;
   t.n_g = p.n_g;
@@ -197,6 +204,7 @@ size_t layout(const dse_params& p, Views* v, char* base) {
   // larger row kind), at least two angles per lane
   t.KS = 1;
   while (t.KS < 8 && (t.RZ > t.RG ? t.RZ : t.RG) * t.nqt * t.KS < 1024 && t.Kp / (4 * t.KS * 2) >= 2) t.KS *= 2;
+  if (ks > 0) t.KS = ks;
   t.Rb = 2 * t.RZ + t.RG;
   t.Rbp = pad_up(t.Rb, 16);
   size_t off = 0;
@@ -239,15 +247,8 @@ size_t layout(const dse_params& p, Views* v, char* base) {
   return off;
 }
 
-}  // namespace dse
-
-namespace {
-
-// Host tables, uploaded once.
-dse_status build_tables(dse_ctx* ctx) {
-  const dse_params& p = ctx->p;
-  const dse::Views& v = ctx->v;
-  const dse::Phys& ph = ctx->ph;
+// Host tables of one problem, uploaded once (synchronises the stream).
+dse_status upload_tables(const dse_params& p, const Views& v, const Phys& ph, hipStream_t st, char* err) {
   const int NJ = v.NJ;
   std::vector<double> y(v.Qp, 1.0), W(v.Qp, 0.0), sq(v.Qp, 0.0);
   std::vector<double> u, wu;
@@ -303,18 +304,60 @@ dse_status build_tables(dse_ctx* ctx) {
     }
   }
   std::vector<double> zeros((size_t)v.KS * v.Rbp * v.Qp, 0.0);
-  hipStream_t st = ctx->st;
-  HIP_TRY(ctx, hipMemcpyAsync(v.y, y.data(), v.Qp * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(v.W, W.data(), v.Qp * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(v.Ttab, Ttab.data(), Ttab.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(v.Text, Text.data(), Text.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(v.xrow, xrow.data(), xrow.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(v.ang, ang.data(), ang.size() * 8, hipMemcpyHostToDevice, st));
-  // the padding rows of B must be finite (they only feed padding rows of Eq)
-  HIP_TRY(ctx, hipMemcpyAsync(v.Bm, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipStreamSynchronize(st));
+  struct { void* dst; const void* src; size_t bytes; } up[] = {
+      {v.y, y.data(), v.Qp * 8u},
+      {v.W, W.data(), v.Qp * 8u},
+      {v.Ttab, Ttab.data(), Ttab.size() * 8},
+      {v.Text, Text.data(), Text.size() * 8},
+      {v.xrow, xrow.data(), xrow.size() * 8},
+      {v.ang, ang.data(), ang.size() * 8},
+      // the padding rows of B must be finite (they only feed padding rows of Eq)
+      {v.Bm, zeros.data(), zeros.size() * 8},
+  };
+  for (auto& u_ : up) {
+    const hipError_t e = hipMemcpyAsync(u_.dst, u_.src, u_.bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) { set_err(err, "table upload: %s", hipGetErrorString(e)); return DSE_E_DEVICE; }
+  }
+  const hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { set_err(err, "table upload: %s", hipGetErrorString(e)); return DSE_E_DEVICE; }
   return DSE_OK;
 }
+
+// Start guess (see dse_start_guess) of one problem into c[n] (host).
+void start_guess_host(const dse_params& p, const Phys& ph, double* c_out) {
+  const double L1 = 0.5 * (ph.ln_lam2 - ph.ln_eps2);
+  const double zl = 1.0 / p.z_lambda_inv;
+  const double r = pow(zl, 1.0 / p.gamma);  // = 1 + omega ln(1 + Lambda^2/mu2)
+  const double mu2 = r > 1.0 + 1e-9 ? p.lambda2 / expm1((r - 1.0) / ph.omega) : 1e6 * p.lambda2;
+  const double m2 = p.g0_inv > 0.0 ? mu2 * pow(p.g0_inv, 1.0 / p.kappa) : 0.0;
+  for (int i = 0; i < p.n_z + p.n_g; ++i) c_out[i] = 0.0;
+  for (int f = 0; f < 2; ++f) {
+    const int N = f == 0 ? p.n_z : p.n_g;
+    double* o = c_out + (f == 0 ? 0 : p.n_z);
+    for (int i = 0; i < N; ++i) {
+      const double phi = kPi * (i + 0.5) / N;
+      const double s = -cos(phi);
+      const double x = exp(ph.L0 + L1 * s);
+      const double L = log1p(ph.omega * log1p(x / mu2));
+      double val;
+      if (f == 0)
+        val = (p.g0_inv > 0.0 ? 1.0 : 2.0 * p.kappa) * log(x / (x + mu2)) + p.gamma * L;
+      else
+        val = -p.kappa * log((x + m2) / (x + mu2)) + p.delta * L;
+      // T_j(-cos phi) = cos(j (pi - phi)) = (-1)^j cos(j phi)
+      for (int j = 0; j < N; ++j) o[j] += (2.0 / N) * val * ((j & 1) ? -1.0 : 1.0) * cos(j * phi);
+    }
+  }
+}
+
+}  // namespace dse
+
+namespace {
+
+using dse::validate;
+using dse::make_phys;
+
+dse_status build_tables(dse_ctx* ctx) { return dse::upload_tables(ctx->p, ctx->v, ctx->ph, ctx->st, ctx->err); }
 
 dse_status check_ctx(const dse_ctx* ctx) { return ctx ? DSE_OK : DSE_E_INVALID; }
 
@@ -374,10 +417,10 @@ dse_status flush_timings(dse_ctx* ctx) {
   return DSE_OK;
 }
 
-// Reads merit, ||F||_2, ||d||_inf and the LU flag (synchronises the stream).
-dse_status read_norms(dse_ctx* ctx, const double* F, const double* S, const double* d, double out[3]) {
+// Reads max_r |F_r|/S_r, ||F||_2, ||d||_inf and ||F/S||_2 (synchronises the stream).
+dse_status read_norms(dse_ctx* ctx, const double* F, const double* S, const double* d, double out[4]) {
   HIP_TRY(ctx, dse::launch_norms(ctx->v, F, S, d, ctx->v.scal, ctx->st));
-  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->v.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->v.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
   return DSE_OK;
 }
@@ -426,7 +469,7 @@ dse_status dse_params_default(dse_params* p) {
 size_t dse_workspace_bytes(const dse_params* p) {
   char tmp[512];
   if (validate(p, tmp) != DSE_OK) return 0;
-  return dse::layout(*p, nullptr, nullptr);
+  return dse::layout(*p, nullptr, nullptr, 0);
 }
 
 dse_status dse_init(const dse_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream,
@@ -439,7 +482,7 @@ dse_status dse_init(const dse_params* p, void* d_workspace, size_t ws_bytes, voi
     set_err(g_init_err, "workspace must be a non-NULL, 256-byte aligned device pointer");
     return DSE_E_INVALID;
   }
-  const size_t need = dse::layout(*p, nullptr, nullptr);
+  const size_t need = dse::layout(*p, nullptr, nullptr, 0);
   if (ws_bytes < need) {
     set_err(g_init_err, "workspace has %zu bytes, needs %zu", ws_bytes, need);
     return DSE_E_NOMEM;
@@ -451,7 +494,7 @@ dse_status dse_init(const dse_params* p, void* d_workspace, size_t ws_bytes, voi
   ctx->st = (hipStream_t)hip_stream;
   ctx->ws = (char*)d_workspace;
   ctx->ws_bytes = ws_bytes;
-  dse::layout(*p, &ctx->v, ctx->ws);
+  dse::layout(*p, &ctx->v, ctx->ws, 0);
   if (hipGetDevice(&ctx->device) != hipSuccess) {
     set_err(g_init_err, "hipGetDevice failed");
     delete ctx;
@@ -502,31 +545,8 @@ dse_status dse_sizes(const dse_ctx* ctx, int32_t* n, int32_t* nr, int32_t* na) {
 dse_status dse_start_guess(dse_ctx* ctx, double* d_c) {
   if (!ctx || !d_c) return DSE_E_INVALID;
   DeviceGuard dg(ctx->device);
-  const dse_params& p = ctx->p;
-  const dse::Phys& ph = ctx->ph;
-  const double L1 = 0.5 * (ph.ln_lam2 - ph.ln_eps2);
-  const double zl = 1.0 / p.z_lambda_inv;
-  const double r = pow(zl, 1.0 / p.gamma);  // = 1 + omega ln(1 + Lambda^2/mu2)
-  const double mu2 = r > 1.0 + 1e-9 ? p.lambda2 / expm1((r - 1.0) / ph.omega) : 1e6 * p.lambda2;
-  const double m2 = p.g0_inv > 0.0 ? mu2 * pow(p.g0_inv, 1.0 / p.kappa) : 0.0;
   std::vector<double> c(ctx->v.n, 0.0);
-  for (int f = 0; f < 2; ++f) {
-    const int N = f == 0 ? p.n_z : p.n_g;
-    double* o = c.data() + (f == 0 ? 0 : p.n_z);
-    for (int i = 0; i < N; ++i) {
-      const double phi = kPi * (i + 0.5) / N;
-      const double s = -cos(phi);
-      const double x = exp(ph.L0 + L1 * s);
-      const double L = log1p(ph.omega * log1p(x / mu2));
-      double val;
-      if (f == 0)
-        val = (p.g0_inv > 0.0 ? 1.0 : 2.0 * p.kappa) * log(x / (x + mu2)) + p.gamma * L;
-      else
-        val = -p.kappa * log((x + m2) / (x + mu2)) + p.delta * L;
-      // T_j(-cos phi) = cos(j (pi - phi)) = (-1)^j cos(j phi)
-      for (int j = 0; j < N; ++j) o[j] += (2.0 / N) * val * ((j & 1) ? -1.0 : 1.0) * cos(j * phi);
-    }
-  }
+  dse::start_guess_host(ctx->p, ctx->ph, c.data());
   HIP_TRY(ctx, hipMemcpyAsync(d_c, c.data(), c.size() * 8, hipMemcpyHostToDevice, ctx->st));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
   return DSE_OK;
@@ -627,11 +647,12 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
   const dse::Views& v = ctx->v;
   const int n = v.n;
   hipStream_t st = ctx->st;
-  double nrm[3];
+  double nrm[4];
   dse_status s = eval_residual(ctx, d_c, v.F, v.S);
   if (s == DSE_OK) s = read_norms(ctx, v.F, v.S, nullptr, nrm);
   ++r.n_residuals;
-  double f = nrm[0];
+  double f = nrm[0];      // convergence test: max_r |F_r| / S_r
+  double f2 = nrm[3];     // line-search merit: ||F / S||_2
   r.fnorm_hist[0] = f;
   int it = 0, extra = 0;
   dse_status status = s;
@@ -648,7 +669,7 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
     if (hipGetLastError() != hipSuccess) { status = DSE_E_DEVICE; break; }
     HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, st));
     const bool conv = f < o.tol;
-    double rho = 1.0, ft = INFINITY, dinf = 0.0;
+    double rho = 1.0, ft = INFINITY, ft2 = INFINITY, dinf = 0.0;
     for (int h = 0;; ++h) {
       HIP_TRY(ctx, dse::launch_axpy(n, d_c, rho, v.dlt, v.ct, st));
       if ((s = eval_residual(ctx, v.ct, v.Ft, v.St)) != DSE_OK) { status = s; break; }
@@ -660,8 +681,9 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
         if (flag == DSE_E_SINGULAR) { status = DSE_E_SINGULAR; set_err(ctx->err, "zero pivot"); break; }
       }
       ft = isfinite(nrm[0]) ? nrm[0] : INFINITY;
+      ft2 = isfinite(nrm[0]) && isfinite(nrm[3]) ? nrm[3] : INFINITY;
       dinf = nrm[2];
-      if (conv || ft < f || h >= o.max_halvings) break;
+      if (conv || ft2 < f2 || h >= o.max_halvings) break;
       rho *= 0.5;
     }
     if (status != DSE_OK) break;
@@ -670,6 +692,7 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
     HIP_TRY(ctx, hipMemcpyAsync(v.F, v.Ft, n * 8, hipMemcpyDeviceToDevice, st));
     HIP_TRY(ctx, hipMemcpyAsync(v.S, v.St, n * 8, hipMemcpyDeviceToDevice, st));
     f = ft;
+    f2 = ft2;
     ++it;
     if (it < 128) { r.fnorm_hist[it] = f; r.relax_hist[it - 1] = rho; }
     r.fnorm2 = nrm[1];

@@ -14,6 +14,7 @@ namespace dse {
 // order).
 constexpr int kQPad = 64;
 constexpr int kKPad = 8;
+constexpr double kPi = 3.14159265358979323846264338327950288;
 
 inline int pad_up(int v, int m) { return (v + m - 1) / m * m; }
 // Padded Chebyshev order: 16, 32, 48, 64, 96 or 128.
@@ -81,7 +82,23 @@ struct Views {
   double* scal;          // [8] merit, ||F||_2, ||delta||_inf
 };
 
-size_t layout(const dse_params& p, Views* v, char* base);  // returns bytes
+// One problem of a batched family as the batched kernels see it (device
+// memory, one per problem).
+struct SolveDesc {
+  Views v;
+  Phys ph;
+  int coff;   // offset of the problem's unknowns in the packed coefficient vector
+  int pad_;
+  size_t joff;  // offset of its n x n Newton matrix in a packed matrix array
+};
+
+// Host helpers (dse_host.hip).
+void set_err(char* buf, const char* fmt, ...);
+dse_status validate(const dse_params* p, char* err);
+Phys make_phys(const dse_params& p);
+size_t layout(const dse_params& p, Views* v, char* base, int ks);  // returns bytes
+dse_status upload_tables(const dse_params& p, const Views& v, const Phys& ph, hipStream_t st, char* err);
+void start_guess_host(const dse_params& p, const Phys& ph, double* c_out);
 
 // Kernel launchers (dse_kernels.hip).  All enqueue on `st`.
 hipError_t launch_dressing(const Views& v, const Phys& ph, const double* c, hipStream_t st);
@@ -102,5 +119,31 @@ hipError_t launch_axpy(int n, const double* c, double rho, const double* d, doub
                        hipStream_t st);
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x,
                            int trans, hipStream_t st);
+
+// Batched family (one launch per stage for all problems whose mask entry is
+// set).  `which` selects the evaluation point and outputs: 0 = the packed
+// coefficients cpk (outputs F, S), 1 = the trial point ct (outputs Ft, St).
+struct BatchArgs {
+  const SolveDesc* desc;  // [count]
+  int count;
+  const int* mask;        // [count] nonzero: problem takes part
+  int max_n, max_np, max_nj, max_rbt;  // largest n, padded n, padded order, contraction row blocks
+};
+hipError_t launch_batch_dressing(const BatchArgs& a, const double* cpk, int which, int* counter,
+                                 hipStream_t st);
+// items: (problem, kind, row, tile), in queue order.  grid = 0: one block per
+// item in queue order; grid > 0: that many persistent blocks take items from
+// the queue through the counter (which the dressing launch resets).
+hipError_t launch_batch_points(const BatchArgs& a, const int4* items, int n_items, int mode, int grid,
+                               int* counter, hipStream_t st);
+int batch_points_occupancy(int mode, int max_nj);  // resident blocks per CU
+hipError_t launch_batch_contract(const BatchArgs& a, hipStream_t st);
+hipError_t launch_batch_assemble(const BatchArgs& a, hipStream_t st);
+hipError_t launch_batch_residual_rows(const BatchArgs& a, int which, hipStream_t st);
+hipError_t launch_batch_norms(const BatchArgs& a, int which, double* out /* [count][4] */, hipStream_t st);
+hipError_t launch_batch_lu(const BatchArgs& a, int* flags /* [count] */, hipStream_t st);
+hipError_t launch_batch_axpy(const BatchArgs& a, const double* cpk, const double* rho, hipStream_t st);
+hipError_t launch_batch_accept(const BatchArgs& a, double* cpk, hipStream_t st);
+hipError_t launch_batch_pack(const BatchArgs& a, double* Jpk, double* Fpk, hipStream_t st);
 
 }  // namespace dse

@@ -69,11 +69,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // --------------------------------------------------------------------------
 // dressing: coef (c_0 halved, zero padded), ln Z / ln G at radial nodes and at
 // the collocation points.
-__global__ __launch_bounds__(256) void dressing_kernel(Views v, Phys ph, const double* __restrict__ c) {
+__device__ __forceinline__ void dressing_body(const Views& v, const Phys& ph, const double* __restrict__ c) {
   __shared__ double sa[DSE_MAX_N], sb[DSE_MAX_N];
   const int t = threadIdx.x;
   const int NJ = v.NJ;
-  for (int j = t; j < NJ; j += blockDim.x) {
+  for (int j = t; j < NJ; j += 256) {
     double a = j < v.n_z ? c[j] : 0.0;
     double b = j < v.n_g ? c[v.n_z + j] : 0.0;
     if (j == 0) { a *= 0.5; b *= 0.5; }
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void dressing_kernel(Views v, Phys ph, const d
   }
   __syncthreads();
   const int nout = v.Qp + v.n;
-  for (int o = t; o < nout; o += blockDim.x) {
+  for (int o = t; o < nout; o += 256) {
     if (o < v.Qp) {
       const double* T = v.Ttab + (size_t)o * NJ;
       double z = 0.0, g = 0.0;
@@ -110,6 +110,10 @@ __global__ __launch_bounds__(256) void dressing_kernel(Views v, Phys ph, const d
       v.lnX[r] = s;  // collocation points lie in [eps2, lambda2]: no extension
     }
   }
+}
+
+__global__ __launch_bounds__(256) void dressing_kernel(Views v, Phys ph, const double* __restrict__ c) {
+  dressing_body(v, ph, c);
 }
 
 // --------------------------------------------------------------------------
@@ -170,8 +174,14 @@ __device__ __forceinline__ void slice_reduce(double* vals, int lane, int& base, 
 // d Pi / d alpha, no B, no D).
 enum { MODE_RES = 0, MODE_JAC = 1, MODE_VJP = 2, MODE_VTH = 3 };
 
+// LDS of one point-kernel block (doubles): red[3][4] at 0, bs[2][4][64] at 16,
+// ds[4][NT*NJ] at 528.
+template <int NJ>
+__host__ __device__ constexpr int point_smem() { return 528 + 8 * NJ; }
+
 template <int KIND, int NJ, int MODE>
-__global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
+__device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int row, int tile,
+                                           double* __restrict__ smem) {
   using TL = Tile<KIND, NJ>;
   constexpr int G = TL::G;
   constexpr int JT = TL::JT;
@@ -183,9 +193,7 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   const int lane = t & 63;
   const int wave = t >> 6;
   const int KS = v.KS;
-  const int ntile = v.nqt * KS;                   // partial tiles per row
-  const int row = blockIdx.x / ntile;
-  const int tile = blockIdx.x - row * ntile;      // = qt * KS + ks
+  const int ntile = v.nqt * KS;                   // partial tiles per row; tile = qt * KS + ks
   const int qt = tile / KS, ks = tile - qt * KS;
   const int q = qt * 64 + lane;
   const int growrow = KIND == GLUON ? row : v.RZ + row;  // index into xrow / Pip
@@ -350,7 +358,7 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   }
 
   // ---- epilogue: residual partials (compensated, as pairs)
-  __shared__ double red[3][4];
+  double (*red)[4] = reinterpret_cast<double (*)[4]>(smem);
   {
     wave_sum2(pi_s, pi_c);
     const double a = wave_sum(abs_acc);
@@ -369,12 +377,12 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   if (!JAC) return;
 
   // ---- q-side: angular sums staged in LDS, reduced over the four waves
-  __shared__ double bs[2][4][64];
+  double (*bs)[4][64] = reinterpret_cast<double (*)[4][64]>(smem + 16);
   bs[0][wave][lane] = Ba;
   bs[1][wave][lane] = Bb;
   // ---- k-side: reduce-scatter over the lanes that hold the same slice, then
   // over the waves through LDS
-  __shared__ double ds[4][NT * NJ];
+  double (*ds)[NT * NJ] = reinterpret_cast<double (*)[NT * NJ]>(smem + 528);
   {
     double vals[NT * JT];
 #pragma unroll
@@ -417,24 +425,33 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   }
 }
 
+// One block per (row, tile): blockIdx.x = row * (nqt KS) + tile.
+template <int KIND, int NJ, int MODE>
+__global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
+  __shared__ double smem[point_smem<NJ>()];
+  const int ntile = v.nqt * v.KS;
+  const int row = blockIdx.x / ntile;
+  point_body<KIND, NJ, MODE>(v, ph, row, blockIdx.x - row * ntile, smem);
+}
+
 // --------------------------------------------------------------------------
 // Eq = B . T on the FP64 matrix cores, plus the k-side sums.  Blocks with
 // blockIdx.x < Rbp/16 compute one 16 x 16 tile of Eq (the four waves split
 // the radial sum and meet in LDS) and add, for gluon rows, the k-side partial
 // sums of the same target; the remaining blocks reduce the ghost rows'
 // k-side partials into Dgh.  Every sum runs in a fixed order.
-__global__ __launch_bounds__(256) void contract_kernel(Views v) {
+__device__ __forceinline__ void contract_body(const Views& v, int bx, int by) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int Qp = v.Qp, NJ = v.NJ;
   const int ntile = v.nqt * v.KS;
   const size_t dstride = (size_t)ntile * NJ;
   const int ntiles_r = v.Rbp / 16;
-  if ((int)blockIdx.x >= ntiles_r) {
+  if (bx >= ntiles_r) {
     // ghost rows, k-side (target a): Dgh[row][j] = sum over tiles
-    const int row0 = ((int)blockIdx.x - ntiles_r) * 16;
+    const int row0 = (bx - ntiles_r) * 16;
     const double* D = v.Dp + (size_t)2 * v.RZ * dstride;
     for (int e = t; e < 16 * 16; e += 256) {
-      const int r = row0 + (e >> 4), j = blockIdx.y * 16 + (e & 15);
+      const int r = row0 + (e >> 4), j = by * 16 + (e & 15);
       if (r < v.RG) {
         const double* src = D + (size_t)r * dstride + j;
         double sum = 0.0;
@@ -444,7 +461,7 @@ __global__ __launch_bounds__(256) void contract_kernel(Views v) {
     }
     return;
   }
-  const int r0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  const int r0 = bx * 16, j0 = by * 16;
   const int qper = Qp / 4;
   const int qbeg = wave * qper;
   const int i = lane & 15, kk = lane >> 4;
@@ -480,6 +497,8 @@ __global__ __launch_bounds__(256) void contract_kernel(Views v) {
     v.Eq[(size_t)row * NJ + col] = sum;
   }
 }
+
+__global__ __launch_bounds__(256) void contract_kernel(Views v) { contract_body(v, blockIdx.x, blockIdx.y); }
 
 // --------------------------------------------------------------------------
 // helpers for assembly: partial sums over the radial tiles, in tile order
@@ -520,9 +539,8 @@ __global__ __launch_bounds__(256) void residual_rows_kernel(Views v, Phys ph, do
 }
 
 // J row r = one block.
-__global__ __launch_bounds__(256) void assemble_kernel(Views v, Phys ph, double* __restrict__ J,
-                                                       double* F, double* S) {
-  const int r = blockIdx.x;
+__device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, int r, double* __restrict__ J,
+                                              double* F, double* S) {
   const int t = threadIdx.x;
   const int NJ = v.NJ, n = v.n;
   const bool gl = r < v.n_z;
@@ -534,7 +552,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(Views v, Phys ph, double*
     const int sub = v.RZ - 1;
     const double* Ea = v.Eq;
     const double* Eb = v.Eq + (size_t)v.RZ * NJ;
-    for (int c = t; c < n; c += blockDim.x) {
+    for (int c = t; c < n; c += 256) {
       double val;
       if (c < v.n_z) {
         val = -d * Tx[c] - Ea[(size_t)i * NJ + c] + Ea[(size_t)sub * NJ + c];
@@ -547,7 +565,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(Views v, Phys ph, double*
   } else {
     const int sub = v.RG - 1;
     const double* Eb = v.Eq + (size_t)2 * v.RZ * NJ;
-    for (int c = t; c < n; c += blockDim.x) {
+    for (int c = t; c < n; c += 256) {
       double val;
       if (c < v.n_z) {
         val = -v.Dgh[(size_t)i * NJ + c] + v.Dgh[(size_t)sub * NJ + c];
@@ -561,38 +579,57 @@ __global__ __launch_bounds__(256) void assemble_kernel(Views v, Phys ph, double*
   if (t == 0 && F) row_residual(v, ph, r, F, S);
 }
 
+__global__ __launch_bounds__(256) void assemble_kernel(Views v, Phys ph, double* __restrict__ J,
+                                                       double* F, double* S) {
+  assemble_body(v, ph, blockIdx.x, J, F, S);
+}
+
 // --------------------------------------------------------------------------
-// merit max_r |F_r| / S_r, ||F||_2 and ||d||_inf (one block).
-__global__ __launch_bounds__(256) void norms_kernel(int n, const double* F, const double* S,
-                                                   const double* d, double* out) {
+// max_r |F_r| / S_r, ||F||_2, ||d||_inf and ||F / S||_2 (one block).
+__device__ __forceinline__ void norms_body(int n, const double* F, const double* S, const double* d,
+                                           double* out) {
   const int t = threadIdx.x;
-  double m = 0.0, s2 = 0.0, dm = 0.0;
+  double m = 0.0, s2 = 0.0, dm = 0.0, q2 = 0.0;
   bool bad = false;
   for (int r = t; r < n; r += 256) {
     const double f = F[r];
     const double sc = S ? S[r] : 0.0;
-    const double q = sc > 0.0 ? fabs(f) / sc : fabs(f);
+    const double qs = sc > 0.0 ? f / sc : f;
+    const double q = fabs(qs);
     if (!(q == q) || isinf(q)) bad = true;
     m = fmax(m, q);
     s2 = fma(f, f, s2);
+    q2 = fma(qs, qs, q2);
     if (d) dm = fmax(dm, fabs(d[r]));
   }
-  __shared__ double sm[256], ss[256], sd[256];
+  __shared__ double sm[256], ss[256], sd[256], sq[256];
   __shared__ int sbad;
   if (t == 0) sbad = 0;
   __syncthreads();
   if (bad) sbad = 1;
-  sm[t] = m; ss[t] = s2; sd[t] = dm;
+  sm[t] = m; ss[t] = s2; sd[t] = dm; sq[t] = q2;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) { sm[t] = fmax(sm[t], sm[t + o]); ss[t] += ss[t + o]; sd[t] = fmax(sd[t], sd[t + o]); }
+    if (t < o) {
+      sm[t] = fmax(sm[t], sm[t + o]);
+      ss[t] += ss[t + o];
+      sd[t] = fmax(sd[t], sd[t + o]);
+      sq[t] += sq[t + o];
+    }
     __syncthreads();
   }
   if (t == 0) {
-    out[0] = sbad ? __longlong_as_double(0x7ff8000000000000LL) : sm[0];
-    out[1] = sqrt(ss[0]);
-    out[2] = sd[0];
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    out[0] = sbad ? nan : sm[0];  // max_r |F_r| / S_r (convergence test)
+    out[1] = sqrt(ss[0]);         // ||F||_2
+    out[2] = sd[0];               // ||d||_inf
+    out[3] = sbad ? nan : sqrt(sq[0]);  // ||F / S||_2 (line-search merit)
   }
+}
+
+__global__ __launch_bounds__(256) void norms_kernel(int n, const double* F, const double* S,
+                                                   const double* d, double* out) {
+  norms_body(n, F, S, d, out);
 }
 
 __global__ void axpy_kernel(int n, const double* c, double rho, const double* d, double* out) {
@@ -749,11 +786,9 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
 }
 
 template <bool IN_LDS, int MR>
-__global__ __launch_bounds__(256) void lu_solve_kernel(int n, const double* __restrict__ Ain,
-                                                       const double* __restrict__ b, double* x,
-                                                       double* __restrict__ Aglob, int* piv,
-                                                       int trans, int* flag) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, const double* __restrict__ b,
+                                        double* x, double* __restrict__ Aglob, int* piv, int trans, int* flag,
+                                        double* lds) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
   const int ld = np + 1;  // column np holds the right-hand side (non-transposed solve)
@@ -980,6 +1015,15 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(int n, const double* __re
   if (lane == 0) flag[0] = 0;
 }
 
+template <bool IN_LDS, int MR>
+__global__ __launch_bounds__(256) void lu_solve_kernel(int n, const double* __restrict__ Ain,
+                                                       const double* __restrict__ b, double* x,
+                                                       double* __restrict__ Aglob, int* piv,
+                                                       int trans, int* flag) {
+  extern __shared__ double lds[];
+  lu_body<IN_LDS, MR>(n, Ain, b, x, Aglob, piv, trans, flag, lds);
+}
+
 // --------------------------------------------------------------------------
 // Vector-Jacobian products.  With row weights rw = -u_i on the collocation
 // rows and rw = sum_i u_i (over the same kind) on the subtraction rows,
@@ -1045,6 +1089,154 @@ __global__ __launch_bounds__(256) void vjp_reduce_kernel(Views v, const double* 
     uth[1] = -sg;       // dF^G/d g0_inv = -1
     uth[2] = -sz;       // dF^Z/d z_lambda_inv = -1
   }
+}
+
+
+// --------------------------------------------------------------------------
+// Batched family: the same bodies, one launch per stage for every problem of
+// the family.  A problem's views and constants come from its descriptor;
+// problems whose mask entry is zero are skipped (converged, or not in the
+// current line-search round).
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__global__ __launch_bounds__(256) void batch_dressing_kernel(const SolveDesc* __restrict__ d,
+                                                             const int* __restrict__ mask,
+                                                             const double* __restrict__ cpk, int which,
+                                                             int* counter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;  // work queue of the next point launch
+  const int b = blockIdx.x;
+  if (!mask[b]) return;
+  const SolveDesc& sd = d[b];
+  dressing_body(sd.v, sd.ph, which ? sd.v.ct : cpk + sd.coff);
+}
+
+// Queue of (problem, kind, row, tile) items, largest first.  The kernel is
+// instantiated for the family's largest padded order and holds a body for
+// every order up to it.
+template <int MODE, int NJMAX>
+__global__ __launch_bounds__(256) void batch_point_kernel(const SolveDesc* __restrict__ d,
+                                                          const int* __restrict__ mask,
+                                                          const int4* __restrict__ items, int n_items,
+                                                          int* counter, int persistent) {
+  __shared__ double smem[point_smem<NJMAX>()];
+  __shared__ int s_item;
+  int it = blockIdx.x;
+  for (;;) {
+    if (persistent) {
+      if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+      __syncthreads();
+      it = uniform(s_item);
+    }
+    if (it >= n_items) break;
+    const int4 w = items[it];
+    const int b = uniform(w.x);
+    if (mask[b]) {
+      const SolveDesc& sd = d[b];
+      const int kind = uniform(w.y), row = uniform(w.z), tile = uniform(w.w);
+      const int nj = uniform(sd.v.NJ);
+#define DSE_BATCH_CASE(N)                                                                   \
+  if constexpr (N <= NJMAX) {                                                               \
+    if (nj == N) {                                                                          \
+      if (kind == GLUON) point_body<GLUON, N, MODE>(sd.v, sd.ph, row, tile, smem);          \
+      else point_body<GHOST, N, MODE>(sd.v, sd.ph, row, tile, smem);                        \
+    }                                                                                       \
+  }
+      DSE_BATCH_CASE(16)
+      DSE_BATCH_CASE(32)
+      DSE_BATCH_CASE(48)
+      DSE_BATCH_CASE(64)
+      DSE_BATCH_CASE(96)
+      DSE_BATCH_CASE(128)
+#undef DSE_BATCH_CASE
+    }
+    if (!persistent) break;
+    __syncthreads();  // the next item reuses s_item and the LDS
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_contract_kernel(const SolveDesc* __restrict__ d,
+                                                             const int* __restrict__ mask) {
+  const int b = blockIdx.z;
+  if (!mask[b]) return;
+  const Views& v = d[b].v;
+  const int bx = blockIdx.x, by = blockIdx.y;
+  if (bx >= v.Rbp / 16 + (v.RG + 15) / 16 || by >= v.NJ / 16) return;
+  contract_body(v, bx, by);
+}
+
+__global__ __launch_bounds__(256) void batch_assemble_kernel(const SolveDesc* __restrict__ d,
+                                                             const int* __restrict__ mask) {
+  const int b = blockIdx.y;
+  if (!mask[b]) return;
+  const SolveDesc& sd = d[b];
+  if ((int)blockIdx.x >= sd.v.n) return;
+  assemble_body(sd.v, sd.ph, blockIdx.x, sd.v.J, sd.v.F, sd.v.S);
+}
+
+__global__ __launch_bounds__(256) void batch_residual_rows_kernel(const SolveDesc* __restrict__ d,
+                                                                  const int* __restrict__ mask, int which) {
+  const int b = blockIdx.y;
+  if (!mask[b]) return;
+  const SolveDesc& sd = d[b];
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r < sd.v.n) row_residual(sd.v, sd.ph, r, which ? sd.v.Ft : sd.v.F, which ? sd.v.St : sd.v.S);
+}
+
+__global__ __launch_bounds__(256) void batch_norms_kernel(const SolveDesc* __restrict__ d,
+                                                          const int* __restrict__ mask, int which,
+                                                          double* out) {
+  const int b = blockIdx.x;
+  if (!mask[b]) return;
+  const Views& v = d[b].v;
+  norms_body(v.n, which ? v.Ft : v.F, which ? v.St : v.S, which ? v.dlt : nullptr, out + 4 * b);
+}
+
+// One workgroup per system: J delta = F.
+template <bool IN_LDS, int MR>
+__global__ __launch_bounds__(256) void batch_lu_kernel(const SolveDesc* __restrict__ d,
+                                                       const int* __restrict__ mask, int* flags) {
+  extern __shared__ double lds[];
+  const int b = blockIdx.x;
+  if (!mask[b]) return;
+  const Views& v = d[b].v;
+  lu_body<IN_LDS, MR>(v.n, v.J, v.F, v.dlt, v.LU, v.piv, 0, flags + b, lds);
+}
+
+__global__ __launch_bounds__(256) void batch_axpy_kernel(const SolveDesc* __restrict__ d,
+                                                         const int* __restrict__ mask,
+                                                         const double* __restrict__ cpk,
+                                                         const double* __restrict__ rho) {
+  const int b = blockIdx.y;
+  if (!mask[b]) return;
+  const SolveDesc& sd = d[b];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < sd.v.n) sd.v.ct[i] = cpk[sd.coff + i] - rho[b] * sd.v.dlt[i];
+}
+
+__global__ __launch_bounds__(256) void batch_accept_kernel(const SolveDesc* __restrict__ d,
+                                                           const int* __restrict__ mask, double* cpk) {
+  const int b = blockIdx.y;
+  if (!mask[b]) return;
+  const SolveDesc& sd = d[b];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < sd.v.n) {
+    cpk[sd.coff + i] = sd.v.ct[i];
+    sd.v.F[i] = sd.v.Ft[i];
+    sd.v.S[i] = sd.v.St[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_pack_kernel(const SolveDesc* __restrict__ d,
+                                                         const int* __restrict__ mask, double* Jpk,
+                                                         double* Fpk) {
+  const int b = blockIdx.y;
+  if (!mask[b]) return;
+  const SolveDesc& sd = d[b];
+  const int n = sd.v.n, r = blockIdx.x;
+  if (r >= n) return;
+  for (int c = threadIdx.x; c < n; c += 256) Jpk[sd.joff + (size_t)r * n + c] = sd.v.J[(size_t)r * n + c];
+  if (Fpk && threadIdx.x == 0) Fpk[sd.coff + r] = sd.v.F[r];
 }
 
 // --------------------------------------------------------------------------
@@ -1165,6 +1357,145 @@ hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, dou
       hipLaunchKernelGGL((lu_solve_kernel<false, 4>), dim3(1), dim3(256), 0, st, n, A, b, x, v.LU, v.piv, trans,
                          v.flag);
   }
+  return hipGetLastError();
+}
+
+
+// ---- batched family
+
+hipError_t launch_batch_dressing(const BatchArgs& a, const double* cpk, int which, int* counter,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(batch_dressing_kernel, dim3(a.count), dim3(256), 0, st, a.desc, a.mask, cpk, which,
+                     counter);
+  return hipGetLastError();
+}
+
+template <int MODE, int NJMAX>
+static hipError_t batch_points_nj(const BatchArgs& a, const int4* items, int n_items, int grid, int* counter,
+                                  hipStream_t st) {
+  const int blocks = grid > 0 ? grid : n_items;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((batch_point_kernel<MODE, NJMAX>), dim3(blocks), dim3(256), 0, st, a.desc, a.mask, items,
+                     n_items, counter, grid > 0 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t batch_points_mode(const BatchArgs& a, const int4* items, int n_items, int grid, int* counter,
+                                    hipStream_t st) {
+  switch (a.max_nj) {
+    case 16: return batch_points_nj<MODE, 16>(a, items, n_items, grid, counter, st);
+    case 32: return batch_points_nj<MODE, 32>(a, items, n_items, grid, counter, st);
+    case 48: return batch_points_nj<MODE, 48>(a, items, n_items, grid, counter, st);
+    case 64: return batch_points_nj<MODE, 64>(a, items, n_items, grid, counter, st);
+    case 96: return batch_points_nj<MODE, 96>(a, items, n_items, grid, counter, st);
+    case 128: return batch_points_nj<MODE, 128>(a, items, n_items, grid, counter, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_points(const BatchArgs& a, const int4* items, int n_items, int mode, int grid,
+                               int* counter, hipStream_t st) {
+  switch (mode) {
+    case MODE_RES: return batch_points_mode<MODE_RES>(a, items, n_items, grid, counter, st);
+    case MODE_JAC: return batch_points_mode<MODE_JAC>(a, items, n_items, grid, counter, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int MODE, int NJMAX>
+static int occ_nj() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)batch_point_kernel<MODE, NJMAX>, 256, 0) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+int batch_points_occupancy(int mode, int max_nj) {
+  const bool jac = mode == MODE_JAC;
+  switch (max_nj) {
+    case 16: return jac ? occ_nj<MODE_JAC, 16>() : occ_nj<MODE_RES, 16>();
+    case 32: return jac ? occ_nj<MODE_JAC, 32>() : occ_nj<MODE_RES, 32>();
+    case 48: return jac ? occ_nj<MODE_JAC, 48>() : occ_nj<MODE_RES, 48>();
+    case 64: return jac ? occ_nj<MODE_JAC, 64>() : occ_nj<MODE_RES, 64>();
+    case 96: return jac ? occ_nj<MODE_JAC, 96>() : occ_nj<MODE_RES, 96>();
+    default: return jac ? occ_nj<MODE_JAC, 128>() : occ_nj<MODE_RES, 128>();
+  }
+}
+
+hipError_t launch_batch_contract(const BatchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(batch_contract_kernel, dim3(a.max_rbt, a.max_nj / 16, a.count), dim3(256), 0, st, a.desc,
+                     a.mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_assemble(const BatchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(batch_assemble_kernel, dim3(a.max_n, a.count), dim3(256), 0, st, a.desc, a.mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_residual_rows(const BatchArgs& a, int which, hipStream_t st) {
+  hipLaunchKernelGGL(batch_residual_rows_kernel, dim3((a.max_n + 255) / 256, a.count), dim3(256), 0, st, a.desc,
+                     a.mask, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_norms(const BatchArgs& a, int which, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(batch_norms_kernel, dim3(a.count), dim3(256), 0, st, a.desc, a.mask, which, out);
+  return hipGetLastError();
+}
+
+template <bool IN_LDS, int MR>
+static void set_batch_lu_lds(int bytes) {
+  (void)hipFuncSetAttribute((const void*)batch_lu_kernel<IN_LDS, MR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+}
+
+hipError_t launch_batch_lu(const BatchArgs& a, int* flags, hipStream_t st) {
+  const int np = a.max_np;
+  const size_t lds_bytes = (size_t)np * (np + 1) * sizeof(double);
+  const size_t static_bytes = 256 * 4 + 256 * 8 + 64;
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0, val = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      val = 64 * 1024;
+    max_lds = val;
+    const int dyn = max_lds - (int)static_bytes;
+    set_batch_lu_lds<true, 2>(dyn);
+    set_batch_lu_lds<true, 4>(dyn);
+  }
+  const bool fits = lds_bytes + static_bytes <= (size_t)max_lds;
+  if (np <= 128) {
+    if (fits)
+      hipLaunchKernelGGL((batch_lu_kernel<true, 2>), dim3(a.count), dim3(256), lds_bytes, st, a.desc, a.mask, flags);
+    else
+      hipLaunchKernelGGL((batch_lu_kernel<false, 2>), dim3(a.count), dim3(256), 0, st, a.desc, a.mask, flags);
+  } else {
+    if (fits)
+      hipLaunchKernelGGL((batch_lu_kernel<true, 4>), dim3(a.count), dim3(256), lds_bytes, st, a.desc, a.mask, flags);
+    else
+      hipLaunchKernelGGL((batch_lu_kernel<false, 4>), dim3(a.count), dim3(256), 0, st, a.desc, a.mask, flags);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_axpy(const BatchArgs& a, const double* cpk, const double* rho, hipStream_t st) {
+  hipLaunchKernelGGL(batch_axpy_kernel, dim3((a.max_n + 255) / 256, a.count), dim3(256), 0, st, a.desc, a.mask,
+                     cpk, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_accept(const BatchArgs& a, double* cpk, hipStream_t st) {
+  hipLaunchKernelGGL(batch_accept_kernel, dim3((a.max_n + 255) / 256, a.count), dim3(256), 0, st, a.desc, a.mask,
+                     cpk);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pack(const BatchArgs& a, double* Jpk, double* Fpk, hipStream_t st) {
+  hipLaunchKernelGGL(batch_pack_kernel, dim3(a.max_n, a.count), dim3(256), 0, st, a.desc, a.mask, Jpk, Fpk);
   return hipGetLastError();
 }
 

@@ -27,6 +27,9 @@ EXPORTS = [
     "dse_residual", "dse_jacobian", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
     "dse_last_error", "dse_sizes", "dse_set_timing", "dse_read_timings", "dse_vjp",
     "dse_set_physics",
+    "dse_batch_workspace_bytes", "dse_batch_init", "dse_batch_destroy", "dse_batch_last_error",
+    "dse_batch_offsets", "dse_batch_start_guess", "dse_batch_jacobian", "dse_batch_newton_solve",
+    "dse_batch_autotune", "dse_batch_set_launch", "dse_batch_get_launch",
 ]
 
 
@@ -52,6 +55,13 @@ class NewtonReport(C.Structure):
                 ("fnorm2", C.c_double), ("fnorm_hist", C.c_double * 128),
                 ("relax_hist", C.c_double * 128), ("n_jacobians", C.c_int32),
                 ("n_residuals", C.c_int32), ("t_total_ms", C.c_double)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("slices", C.c_int32), ("persistent_blocks", C.c_int32), ("order", C.c_int32),
+                ("n_candidates", C.c_int32), ("best_ms", C.c_double),
+                ("cand_slices", C.c_int32 * 32), ("cand_blocks", C.c_int32 * 32),
+                ("cand_order", C.c_int32 * 32), ("cand_ms", C.c_double * 32)]
 
 
 class DSEError(RuntimeError):
@@ -89,6 +99,18 @@ def load():
             "dse_read_timings": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
             "dse_vjp": (C.c_int, [vp, vp, vp, vp, vp]),
             "dse_set_physics": (C.c_int, [vp, C.c_double, C.c_double, C.c_double]),
+            "dse_batch_workspace_bytes": (C.c_size_t, [P, C.c_int32]),
+            "dse_batch_init": (C.c_int, [P, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]),
+            "dse_batch_destroy": (C.c_int, [vp]),
+            "dse_batch_last_error": (C.c_char_p, [vp]),
+            "dse_batch_offsets": (C.c_int, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+            "dse_batch_start_guess": (C.c_int, [vp, vp]),
+            "dse_batch_jacobian": (C.c_int, [vp, vp, vp, vp]),
+            "dse_batch_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
+            "dse_batch_autotune": (C.c_int, [vp, vp, C.POINTER(BatchTuning)]),
+            "dse_batch_set_launch": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
+            "dse_batch_get_launch": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                               C.POINTER(C.c_int32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -266,3 +288,133 @@ class Solver:
         n, nr, na = C.c_int32(), C.c_int32(), C.c_int32()
         self._check(self.lib.dse_sizes(self.h, C.byref(n), C.byref(nr), C.byref(na)))
         return n.value, nr.value, na.value
+
+
+def _report(rep: NewtonReport, c) -> NewtonResult:
+    return NewtonResult(c=c, status=rep.status, iters=rep.iters, fnorm=rep.fnorm, fnorm2=rep.fnorm2,
+                        fnorm_hist=list(rep.fnorm_hist[: rep.iters + 1]),
+                        relax_hist=list(rep.relax_hist[: rep.iters]), n_jacobians=rep.n_jacobians,
+                        n_residuals=rep.n_residuals, t_total_ms=rep.t_total_ms)
+
+
+class Batch:
+    """A family of independent problems assembled and solved together.
+
+    ``problems`` is a list of keyword dicts (each as for Solver).  Unknowns of
+    all problems live in one packed float64 vector (problem b at
+    ``off_c[b]:off_c[b+1]``), Newton matrices in one packed array
+    (``off_J[b]:off_J[b+1]``, row-major n_b x n_b)."""
+
+    def __init__(self, problems, device="cuda", stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP solver needs a GPU")
+        self.lib = load()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.count = len(problems)
+        arr = (Params * self.count)()
+        for i, kw in enumerate(problems):
+            arr[i] = params(**kw)
+        self.params = arr
+        nbytes = self.lib.dse_batch_workspace_bytes(arr, self.count)
+        if nbytes == 0:
+            h = C.c_void_p()
+            st = self.lib.dse_batch_init(arr, self.count, None, 0, None, C.byref(h))
+            raise DSEError(st, self.lib.dse_batch_last_error(None).decode())
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self.ws.data_ptr() + 255) // 256 * 256
+            h = C.c_void_p()
+            st = self.lib.dse_batch_init(arr, self.count, C.c_void_p(ptr), nbytes,
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st:
+            raise DSEError(st, self.lib.dse_batch_last_error(None).decode())
+        self.h = h
+        oc = (C.c_int64 * (self.count + 1))()
+        oj = (C.c_int64 * (self.count + 1))()
+        self._check(self.lib.dse_batch_offsets(self.h, oc, oj))
+        self.off_c = list(oc)
+        self.off_J = list(oj)
+
+    def _check(self, st):
+        if st:
+            raise DSEError(st, self.lib.dse_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dse_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _packed(self, c=None):
+        n = self.off_c[-1]
+        if c is None:
+            return torch.empty(n, dtype=torch.float64, device=self.device)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        if c.shape != (n,):
+            raise ValueError("expected a packed vector of length %d" % n)
+        return c
+
+    def split(self, packed):
+        """Per-problem views of a packed vector."""
+        return [packed[self.off_c[b]: self.off_c[b + 1]] for b in range(self.count)]
+
+    def split_J(self, packed):
+        out = []
+        for b in range(self.count):
+            n = self.off_c[b + 1] - self.off_c[b]
+            out.append(packed[self.off_J[b]: self.off_J[b + 1]].view(n, n))
+        return out
+
+    def start_guess(self):
+        c = self._packed()
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_batch_start_guess(self.h, _ptr(c)))
+        return c
+
+    def jacobian(self, c):
+        c = self._packed(c)
+        J = torch.empty(self.off_J[-1], dtype=torch.float64, device=self.device)
+        F = self._packed()
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_batch_jacobian(self.h, _ptr(c), _ptr(J), _ptr(F)))
+        return J, F
+
+    def newton(self, c0=None, tol=1e-10, max_iter=60, extra_iters=0, max_halvings=30,
+               step_tol=1e-14, raise_on_error: bool = True):
+        c = self.start_guess() if c0 is None else self._packed(c0).clone()
+        o = NewtonOpts(tol=tol, max_iter=max_iter, extra_iters=extra_iters,
+                       max_halvings=max_halvings, step_tol=step_tol)
+        reps = (NewtonReport * self.count)()
+        with torch.cuda.device(self.device):
+            st = self.lib.dse_batch_newton_solve(self.h, _ptr(c), C.byref(o), reps)
+        if st and raise_on_error:
+            self._check(st)
+        cs = self.split(c)
+        return c, [_report(reps[b], cs[b]) for b in range(self.count)]
+
+    def autotune(self, c):
+        c = self._packed(c)
+        r = BatchTuning()
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_batch_autotune(self.h, _ptr(c), C.byref(r)))
+        cands = [dict(slices=r.cand_slices[i], persistent_blocks=r.cand_blocks[i],
+                      order=r.cand_order[i], ms=r.cand_ms[i]) for i in range(r.n_candidates)]
+        return dict(slices=r.slices, persistent_blocks=r.persistent_blocks, order=r.order,
+                    best_ms=r.best_ms, candidates=cands)
+
+    def set_launch(self, slices=1, persistent_blocks=0, order=1):
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_batch_set_launch(self.h, slices, persistent_blocks, order))
+
+    def get_launch(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.dse_batch_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(slices=a.value, persistent_blocks=b.value, order=c.value)
