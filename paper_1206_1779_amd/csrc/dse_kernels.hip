@@ -657,6 +657,16 @@ __global__ void axpy_kernel(int n, const double* c, double rho, const double* d,
 // with wave 0 after the factorisation.
 constexpr int LU_NB = 16;
 
+// Lanes of one wave exchanging values through memory: the stores before this
+// point are visible to every lane's loads after it (release + acquire at
+// wavefront scope; also a compiler barrier, so loads are not hoisted above a
+// store made by another lane).
+__device__ __forceinline__ void wave_memory_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
@@ -683,13 +693,17 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
   return fmax(fmax(r0, r1), fmax(r2, r3));
 }
 
-// One panel column at compile-time register offset O: P[m][O] is column kc.
-// Register rows never move: lpos[m] is the row position a register row holds
-// after the interchanges so far (rows interchange logically in registers and
-// physically in LDS, so the stored factors keep whole-row-interchange order).
-template <int MR, int O>
+// One panel column.  The panel's registers shift left by four after every
+// group of four columns, so with group offset G (compile time) register cc
+// holds column k0 + G + cc for cc < LU_NB - G, and P[m][O] is column
+// kc = k0 + G + O.  Register rows never move: lpos[m] is the row position a
+// register row holds after the interchanges so far (rows interchange
+// logically in registers and physically in memory, so the stored factors keep
+// whole-row-interchange order).
+template <int MR, int O, int G>
 __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], double* M, int ld, int ncol,
                                        int lane, int k0, int kc, int* spiv, int& sing) {
+  constexpr int CE = LU_NB - G;  // registers holding columns of this panel
   double cand[MR];
   double lmax = -1.0;
 #pragma unroll
@@ -721,17 +735,18 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
     mk[m] = __ballot(lpos[m] == p);
     if (mk[m]) { lp = (int)__builtin_ctzll(mk[m]); mp = m; }
   }
-  // the pivot row's panel entries [kc, k0 + LU_NB) are a row of U: the lane
-  // holding it writes them to row kc (those columns of row kc are not read
-  // again from memory before the panel is written back), and every lane reads
+  // the pivot row's panel entries, columns [kc, k0 + LU_NB), are a row of U:
+  // the lane holding it writes them to row kc (memory columns of the panel
+  // are only written while the panel is in registers), and every lane reads
   // them back below, which is also the broadcast
+  double* __restrict__ Ukc = M + (size_t)kc * ld + kc - O;  // Ukc[cc]: column of register cc
   if (lane == lp) {
 #pragma unroll
-    for (int cc = O; cc < LU_NB; ++cc) {
+    for (int cc = O; cc < CE; ++cc) {
       double sel = P[0][cc];
 #pragma unroll
       for (int m = 1; m < MR; ++m) if (mp == m) sel = P[m][cc];
-      M[(size_t)kc * ld + k0 + cc] = sel;
+      Ukc[cc] = sel;
     }
   }
   if (p != kc) {
@@ -768,11 +783,10 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
       }
     }
   }
-  __builtin_amdgcn_s_waitcnt(0);
-  __builtin_amdgcn_wave_barrier();
-  double rp[LU_NB];
+  wave_memory_sync();
+  double rp[CE];
 #pragma unroll
-  for (int cc = O; cc < LU_NB; ++cc) rp[cc] = M[(size_t)kc * ld + k0 + cc];
+  for (int cc = O; cc < CE; ++cc) rp[cc] = Ukc[cc];
   const double dinv_src = rp[O];
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
@@ -780,8 +794,31 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
       const double l = P[m][O] / dinv_src;
       M[(size_t)lpos[m] * ld + kc] = l;
 #pragma unroll
-      for (int cc = O + 1; cc < LU_NB; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
+      for (int cc = O + 1; cc < CE; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
     }
+  }
+}
+
+// Columns G .. LU_NB - 1 of the panel, four at a time (registers shift by four
+// between groups).
+template <int MR, int G>
+__device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR], double* M, int ld, int ncol,
+                                         int lane, int k0, int* spiv, int& sg) {
+  lu_col<MR, 0, G>(P, lpos, M, ld, ncol, lane, k0, k0 + G + 0, spiv, sg);
+  if (sg) return;
+  lu_col<MR, 1, G>(P, lpos, M, ld, ncol, lane, k0, k0 + G + 1, spiv, sg);
+  if (sg) return;
+  lu_col<MR, 2, G>(P, lpos, M, ld, ncol, lane, k0, k0 + G + 2, spiv, sg);
+  if (sg) return;
+  lu_col<MR, 3, G>(P, lpos, M, ld, ncol, lane, k0, k0 + G + 3, spiv, sg);
+  if (sg) return;
+  if constexpr (G + 4 < LU_NB) {
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+#pragma unroll
+      for (int cc = 0; cc < LU_NB - G - 4; ++cc) P[m][cc] = P[m][cc + 4];
+    }
+    lu_panel<MR, G + 4>(P, lpos, M, ld, ncol, lane, k0, spiv, sg);
   }
 }
 
@@ -834,21 +871,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       }
       // four groups of four columns: compile-time offsets inside a group,
       // the group's columns shift to the front afterwards
-      for (int g = 0; g < LU_NB; g += 4) {
-        lu_col<MR, 0>(P, lpos, M, ld, ncol, lane, k0, k0 + g + 0, spiv, sg);
-        if (sg) break;
-        lu_col<MR, 1>(P, lpos, M, ld, ncol, lane, k0, k0 + g + 1, spiv, sg);
-        if (sg) break;
-        lu_col<MR, 2>(P, lpos, M, ld, ncol, lane, k0, k0 + g + 2, spiv, sg);
-        if (sg) break;
-        lu_col<MR, 3>(P, lpos, M, ld, ncol, lane, k0, k0 + g + 3, spiv, sg);
-        if (sg) break;
-#pragma unroll
-        for (int m = 0; m < MR; ++m) {
-#pragma unroll
-          for (int cc = 0; cc < LU_NB - 4; ++cc) P[m][cc] = P[m][cc + 4];
-        }
-      }
+      lu_panel<MR, 0>(P, lpos, M, ld, ncol, lane, k0, spiv, sg);
       if (sg && lane == 0) sing = 1;
     }
     __syncthreads();
@@ -992,15 +1015,13 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       const int r = lane + 64 * m;
       if (r < np) wsv[r] = w[m];
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    wave_memory_sync();
     if (lane == 0)
       for (int k = np - 1; k >= 0; --k) {
         const int pk = spiv[k];
         const double tmp = wsv[k]; wsv[k] = wsv[pk]; wsv[pk] = tmp;
       }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    wave_memory_sync();
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
       const int r = lane + 64 * m;
