@@ -7,8 +7,13 @@ point kernels, B.T contraction on MFMA, assembly), the FP64 LU solve of
 J Delta = F, and the residual at c - Delta.  value = Newton-matrix entries
 (n^2 = 128^2) per second of step time.
 
+Beside it: seconds per Newton solve at N = 64, the 256-problem family solved
+batched against the plain path per problem, and the implicit-function gradient
+against finite differences of re-solves (each on the same GPU, at equal
+convergence).
+
 Prints one JSON line (rank 0).  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 from __future__ import annotations
 
@@ -71,6 +76,100 @@ def cpu_baseline(cfg: dict, c, cpu_seconds: float = 20.0, max_steps: int = 50) -
                       "workload at the start guess, %d host threads" % (steps, threads)}
 
 
+def bench_batched(dse, workloads, torch) -> dict:
+    """The 256-problem family (G(0) log-uniform in [5, 50], N_Z, N_G in
+    {32, 48, 64}, 256+64 x 64) solved by one batched Newton iteration against
+    the plain path run once per problem (one context per (N_Z, N_G), G(0) set
+    per problem), both from the asymptotic start to scaled residual < 1e-10."""
+    fam = workloads.family(256)
+    b = dse.Batch(fam)
+    c0 = b.start_guess()
+    tune = b.autotune(c0)
+    b.newton(c0.clone())  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, res = b.newton(c0.clone())
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    solvers = {}
+    for f in fam:
+        key = (f["n_z"], f["n_g"])
+        if key not in solvers:
+            solvers[key] = dse.Solver(**f)
+            solvers[key].newton()  # warm-up
+    t_plain, iters_plain, dmax = 0.0, [], 0.0
+    for i, f in enumerate(fam):
+        s = solvers[(f["n_z"], f["n_g"])]
+        s.set_physics(g0_inv=f["g0_inv"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.newton()
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        iters_plain.append(r.iters)
+        d = float((r.c - res[i].c).abs().max() / r.c.abs().max())
+        dmax = max(dmax, d)
+    entries = sum((f["n_z"] + f["n_g"]) ** 2 for f in fam)
+    return {"problems": len(fam), "batched_s": t_batch, "plain_s": t_plain, "speedup": t_plain / t_batch,
+            "all_converged": all(r.status == 0 for r in res),
+            "iters_batched_max": max(r.iters for r in res), "iters_plain_max": max(iters_plain),
+            "max_rel_coeff_diff_vs_plain": dmax, "jacobian_entries_per_round": entries,
+            "assembly_round_ms": tune["best_ms"],
+            "assembly_entries_per_s": entries / (tune["best_ms"] * 1e-3),
+            "launch": {k: tune[k] for k in ("slices", "persistent_blocks", "order")},
+            "launch_candidates": tune["candidates"]}
+
+
+def bench_adjoint(dse, workloads, torch) -> dict:
+    """Gradient of L = sum_m ln Z(p_m)^2 (64 log-spaced p in [1e-4, 1e4]) with
+    respect to alpha(mu^2) and G(0) at N = 64: the implicit-function VJP (one
+    Newton matrix at the root, one transposed LU solve, one parameter VJP)
+    against central differences of full re-solves (four Newton solves, h = 1e-6),
+    both after the same converged solve."""
+    from paper_1206_1779_amd.adjoint import chebyshev_basis
+    cfg = workloads.config("cfg5")
+    s = dse.Solver(**cfg)
+    B = chebyshev_basis(s, workloads.adjoint_loss_points(), "Z")
+    nz = cfg["n_z"]
+    r = s.newton()
+    c = r.c
+
+    def ift():
+        lnz = B @ c[:nz]
+        gc = torch.zeros_like(c)
+        gc[:nz] = 2.0 * (lnz @ B)
+        J = s.jacobian(c, with_F=False)
+        lam = s.lu_solve(J, gc, trans=True)
+        _, ut = s.vjp(c, lam, with_c=False)
+        return -ut
+
+    def loss(alpha, g0_inv):
+        s.set_physics(alpha_mu=alpha, g0_inv=g0_inv)
+        rr = s.newton(c0=c)
+        return float(((B @ rr.c[:nz]) ** 2).sum())
+
+    ift()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = ift()
+    torch.cuda.synchronize()
+    t_ift = time.perf_counter() - t0
+    a0, gi0 = cfg["alpha_mu"], cfg["g0_inv"]
+    G0, h = 1.0 / gi0, 1e-6
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fd_a = (loss(a0 + h, gi0) - loss(a0 - h, gi0)) / (2 * h)
+    fd_g = (loss(a0, 1.0 / (G0 + h)) - loss(a0, 1.0 / (G0 - h))) / (2 * h)
+    torch.cuda.synchronize()
+    t_fd = time.perf_counter() - t0
+    s.set_physics(alpha_mu=a0, g0_inv=gi0)
+    g = g.cpu().tolist()
+    dG0 = -g[1] / G0 ** 2
+    return {"ift_s": t_ift, "fd_s": t_fd, "speedup": t_fd / t_ift,
+            "dL_dalpha": {"ift": g[0], "fd": fd_a, "rel_diff": abs(g[0] - fd_a) / abs(fd_a)},
+            "dL_dG0": {"ift": dG0, "fd": fd_g, "rel_diff": abs(dG0 - fd_g) / abs(fd_g)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +177,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--solves", type=int, default=5, help="Newton solves timed for s/solve")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and has no "
@@ -151,6 +251,9 @@ def main() -> int:
         "newton_solve_s": statistics.median(times), "newton_iters": iters[0],
         "roofline": roof,
     }
+    if not args.no_extras:
+        out["batched"] = bench_batched(dse, workloads, torch)
+        out["adjoint"] = bench_adjoint(dse, workloads, torch)
     if not args.no_cpu:
         cb = cpu_baseline(cfg, c.cpu().numpy())
         cb["gpu_speedup"] = value / cb["value"]

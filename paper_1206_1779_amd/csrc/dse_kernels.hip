@@ -639,33 +639,27 @@ __global__ void axpy_kernel(int n, const double* c, double rho, const double* d,
 
 // --------------------------------------------------------------------------
 // FP64 LU with partial pivoting and the triangular solves, one workgroup of
-// four waves, matrix in LDS (or global memory when it does not fit).
-// The matrix is padded to np = 16 ceil(n/16) with an identity block (the
-// padded rows have zeros in the real columns, so they are never chosen as a
-// pivot and the real factors are unchanged) and augmented with the
-// right-hand side as column np.  Blocked right-looking elimination, panel
+// four waves; the padded matrix [A | b] lives in LDS (or in global memory
+// when it does not fit).  The matrix is padded to np = 16 ceil(n/16) with an
+// identity block (padded rows have zeros in the real columns, so they are
+// never chosen as a pivot and the real factors are unchanged) and the
+// right-hand side is column np.  Blocked right-looking elimination, panel
 // width 16:
-//   panel    wave 0 keeps the panel rows (MR per lane) in registers and
-//            factors it column by column: pivot = first row of largest |a|
-//            (lane maxima, DPP rotate-max within rows, ballot for the first
-//            row), whole-row interchange (registers for the panel's remaining
-//            columns, LDS for the rest), multipliers a / pivot, rank-1 update;
-//   U12      U12 = L11^{-1} A12, one column per thread, in registers;
-//   update   A22 -= L21 U12 by all four waves.
-// The right-hand side column ends as L^{-1} P b; wave 0 back-substitutes by
-// blocks of 16 rows.  The transposed solve (A^T x = b) runs U^T, L^T and P^T
-// with wave 0 after the factorisation.
+//   panel    wave 0 holds the rows of the panel (MR per lane) in registers
+//            and factors it column by column: pivot = largest |a| (wave
+//            maximum by DPP; among equal maxima the first register row), the
+//            pivot row's entries broadcast through LDS, multipliers
+//            a * (1 / pivot), rank-1 update.  Interchanges are only recorded
+//            (a register row carries its logical position); the panel's
+//            columns go back to memory by physical row;
+//   swaps    the panel's interchanges, applied to every column at once;
+//   U12      U12 = L11^{-1} A12, one column per thread;
+//   update   A22 -= L21 U12 on v_mfma_f64_16x16x4f64 (16 x 16 tiles over
+//            the four waves); the right-hand-side column on the vector ALUs.
+// The right-hand-side column ends as L^{-1} P b; wave 0 back-substitutes by
+// blocks of 16 rows with the reciprocal pivots kept from the panels.  The
+// transposed solve (A^T x = b) runs U^T, L^T and P^T with wave 0.
 constexpr int LU_NB = 16;
-
-// Lanes of one wave exchanging values through memory: the stores before this
-// point are visible to every lane's loads after it (release + acquire at
-// wavefront scope; also a compiler barrier, so loads are not hoisted above a
-// store made by another lane).
-__device__ __forceinline__ void wave_memory_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const long long b = __double_as_longlong(v);
@@ -674,35 +668,57 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int CTRL>
+template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_d(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  const int lo0 = (int)(b & 0xffffffffLL), hi0 = (int)(b >> 32);
+  // lanes of rows outside ROW_MASK keep their own value
+  const int lo = __builtin_amdgcn_update_dpp(lo0, lo0, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(hi0, hi0, CTRL, ROW_MASK, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Maximum of v over the wave, returned uniformly (v >= 0 or -1 for none).
+// Maximum of v over the wave, returned uniformly (v >= 0, or -1 for none):
+// rotations within rows of 16 lanes, then row broadcasts; lane 63 ends with
+// the maximum of all four rows.
 __device__ __forceinline__ double wave_max_nonneg(double v) {
-  v = fmax(v, dpp_d<0x121>(v));  // row_ror:1
-  v = fmax(v, dpp_d<0x122>(v));  // row_ror:2
-  v = fmax(v, dpp_d<0x124>(v));  // row_ror:4
-  v = fmax(v, dpp_d<0x128>(v));  // row_ror:8
-  const double r0 = readlane_d(v, 0), r1 = readlane_d(v, 16);
-  const double r2 = readlane_d(v, 32), r3 = readlane_d(v, 48);
-  return fmax(fmax(r0, r1), fmax(r2, r3));
+  v = fmax(v, dpp_d<0x121, 0xf>(v));  // row_ror:1
+  v = fmax(v, dpp_d<0x122, 0xf>(v));  // row_ror:2
+  v = fmax(v, dpp_d<0x124, 0xf>(v));  // row_ror:4
+  v = fmax(v, dpp_d<0x128, 0xf>(v));  // row_ror:8
+  v = fmax(v, dpp_d<0x142, 0xa>(v));  // row_bcast:15 into rows 1 and 3
+  v = fmax(v, dpp_d<0x143, 0xc>(v));  // row_bcast:31 into rows 2 and 3
+  return readlane_d(v, 63);
 }
+
+// Lanes of one wave exchanging values through memory: the stores before this
+// point are visible to every lane's loads after it (release + acquire at
+// wavefront scope; also a compiler barrier, so no load is hoisted above a
+// store made by another lane).
+__device__ __forceinline__ void wave_memory_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Shared state of one factorisation.
+struct LUShared {
+  int spiv[256];     // spiv[k]: position interchanged with k at step k
+  double dinv[256];  // 1 / U[k][k]
+  double wsv[256];   // staging of the transposed solve
+  double ub[LU_NB];  // pivot row broadcast
+  int mv_src[2 * LU_NB], mv_dst[2 * LU_NB];  // rows moved by a panel's interchanges
+  int nmv;
+  int sing;
+};
 
 // One panel column.  The panel's registers shift left by four after every
 // group of four columns, so with group offset G (compile time) register cc
 // holds column k0 + G + cc for cc < LU_NB - G, and P[m][O] is column
-// kc = k0 + G + O.  Register rows never move: lpos[m] is the row position a
-// register row holds after the interchanges so far (rows interchange
-// logically in registers and physically in memory, so the stored factors keep
-// whole-row-interchange order).
+// kc = k0 + G + O.  lpos[m] is the logical position of register row m.
 template <int MR, int O, int G>
-__device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], double* M, int ld, int ncol,
-                                       int lane, int k0, int kc, int* spiv, int& sing) {
+__device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], LUShared& sh, int lane,
+                                       int kc, int& sing) {
   constexpr int CE = LU_NB - G;  // registers holding columns of this panel
   double cand[MR];
   double lmax = -1.0;
@@ -713,112 +729,80 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
   }
   const double gmax = wave_max_nonneg(lmax);
   if (!(gmax > 0.0) || isinf(gmax)) { sing = 1; return; }
-  // first row position (after interchanges) holding the maximum
-  int best_pos = 1 << 30;
-#pragma unroll
-  for (int m = 0; m < MR; ++m)
-    if (cand[m] == gmax) best_pos = min(best_pos, lpos[m]);
-  // wave minimum of best_pos (integers, DPP rotate-min within rows + lane reads)
-  int bp = best_pos;
-  bp = min(bp, __builtin_amdgcn_update_dpp(0, bp, 0x121, 0xf, 0xf, false));
-  bp = min(bp, __builtin_amdgcn_update_dpp(0, bp, 0x122, 0xf, 0xf, false));
-  bp = min(bp, __builtin_amdgcn_update_dpp(0, bp, 0x124, 0xf, 0xf, false));
-  bp = min(bp, __builtin_amdgcn_update_dpp(0, bp, 0x128, 0xf, 0xf, false));
-  const int p = min(min(__builtin_amdgcn_readlane(bp, 0), __builtin_amdgcn_readlane(bp, 16)),
-                    min(__builtin_amdgcn_readlane(bp, 32), __builtin_amdgcn_readlane(bp, 48)));
-  if (lane == 0) spiv[kc] = p;
-  // physical register row holding position p
-  unsigned long long mk[MR];
-  int lp = 0, mp = 0;
+  // first register row (m, then lane) holding the maximum
+  int lp = -1, mp = 0;
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
-    mk[m] = __ballot(lpos[m] == p);
-    if (mk[m]) { lp = (int)__builtin_ctzll(mk[m]); mp = m; }
+    const unsigned long long mk = __ballot(cand[m] == gmax);
+    if (lp < 0 && mk) { lp = (int)__builtin_ctzll(mk); mp = m; }
   }
-  // the pivot row's panel entries, columns [kc, k0 + LU_NB), are a row of U:
-  // the lane holding it writes them to row kc (memory columns of the panel
-  // are only written while the panel is in registers), and every lane reads
-  // them back below, which is also the broadcast
-  double* __restrict__ Ukc = M + (size_t)kc * ld + kc - O;  // Ukc[cc]: column of register cc
+  int lsel = lpos[0];
+#pragma unroll
+  for (int m = 1; m < MR; ++m) if (mp == m) lsel = lpos[m];
+  const int p = __builtin_amdgcn_readlane(lsel, lp);
+  wave_memory_sync();  // the previous column's reads of ub are done
   if (lane == lp) {
 #pragma unroll
     for (int cc = O; cc < CE; ++cc) {
       double sel = P[0][cc];
 #pragma unroll
       for (int m = 1; m < MR; ++m) if (mp == m) sel = P[m][cc];
-      Ukc[cc] = sel;
+      sh.ub[cc] = sel;
     }
   }
+  if (lane == 0) sh.spiv[kc] = p;
   if (p != kc) {
-    // logical interchange of the register rows
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
       if (lpos[m] == kc) lpos[m] = p;
       else if (lpos[m] == p) lpos[m] = kc;
     }
-    // physical interchange of the two rows outside the columns in registers
-    const int jhi = k0 + LU_NB;
-    double a[3], bb[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int j = lane + 64 * u;
-      const bool ok = j < ncol && (j < kc || j >= jhi);
-      a[u] = ok ? M[(size_t)kc * ld + j] : 0.0;
-      bb[u] = ok ? M[(size_t)p * ld + j] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int j = lane + 64 * u;
-      if (j < ncol && (j < kc || j >= jhi)) {
-        M[(size_t)kc * ld + j] = bb[u];
-        M[(size_t)p * ld + j] = a[u];
-      }
-    }
-    for (int j = lane + 192; j < ncol; j += 64) {  // ncol > 192 (n > 191)
-      if (j < kc || j >= jhi) {
-        const double x0 = M[(size_t)kc * ld + j];
-        const double x1 = M[(size_t)p * ld + j];
-        M[(size_t)kc * ld + j] = x1;
-        M[(size_t)p * ld + j] = x0;
-      }
-    }
   }
   wave_memory_sync();
   double rp[CE];
 #pragma unroll
-  for (int cc = O; cc < CE; ++cc) rp[cc] = Ukc[cc];
-  const double dinv_src = rp[O];
+  for (int cc = O; cc < CE; ++cc) rp[cc] = sh.ub[cc];
+  const double inv = 1.0 / rp[O];
+  if (lane == 0) sh.dinv[kc] = inv;
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     if (lpos[m] > kc) {
-      const double l = P[m][O] / dinv_src;
-      M[(size_t)lpos[m] * ld + kc] = l;
+      const double l = P[m][O] * inv;
+      P[m][O] = l;
 #pragma unroll
       for (int cc = O + 1; cc < CE; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
     }
   }
 }
 
-// Columns G .. LU_NB - 1 of the panel, four at a time (registers shift by four
-// between groups).
+// Columns G .. LU_NB - 1 of the panel, four at a time; each group's four
+// finished columns go back to memory (by physical row) before the shift.
 template <int MR, int G>
-__device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR], double* M, int ld, int ncol,
-                                         int lane, int k0, int* spiv, int& sg) {
-  lu_col<MR, 0, G>(P, lpos, M, ld, ncol, lane, k0, k0 + G + 0, spiv, sg);
+__device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR], double* M, int ld, int lane,
+                                         int k0, LUShared& sh, int& sg) {
+  lu_col<MR, 0, G>(P, lpos, sh, lane, k0 + G + 0, sg);
   if (sg) return;
-  lu_col<MR, 1, G>(P, lpos, M, ld, ncol, lane, k0, k0 + G + 1, spiv, sg);
+  lu_col<MR, 1, G>(P, lpos, sh, lane, k0 + G + 1, sg);
   if (sg) return;
-  lu_col<MR, 2, G>(P, lpos, M, ld, ncol, lane, k0, k0 + G + 2, spiv, sg);
+  lu_col<MR, 2, G>(P, lpos, sh, lane, k0 + G + 2, sg);
   if (sg) return;
-  lu_col<MR, 3, G>(P, lpos, M, ld, ncol, lane, k0, k0 + G + 3, spiv, sg);
+  lu_col<MR, 3, G>(P, lpos, sh, lane, k0 + G + 3, sg);
   if (sg) return;
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    if (lpos[m] >= 0) {
+      double* Mr = M + (size_t)(k0 + lane + 64 * m) * ld + k0 + G;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) Mr[cc] = P[m][cc];
+    }
+  }
   if constexpr (G + 4 < LU_NB) {
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
 #pragma unroll
       for (int cc = 0; cc < LU_NB - G - 4; ++cc) P[m][cc] = P[m][cc + 4];
     }
-    lu_panel<MR, G + 4>(P, lpos, M, ld, ncol, lane, k0, spiv, sg);
+    lu_panel<MR, G + 4>(P, lpos, M, ld, lane, k0, sh, sg);
   }
 }
 
@@ -826,57 +810,92 @@ template <bool IN_LDS, int MR>
 __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, const double* __restrict__ b,
                                         double* x, double* __restrict__ Aglob, int* piv, int trans, int* flag,
                                         double* lds) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
-  const int ld = np + 1;  // column np holds the right-hand side (non-transposed solve)
+  const int ld = np + 1;  // odd: column accesses spread over the banks
   const int ncol = np + 1;
   double* M = IN_LDS ? lds : Aglob;
-  __shared__ int spiv[256];
-  __shared__ int sing;
-  __shared__ double wsv[256];
-  // load [A | b] padded with an identity block; eight rows per wave in flight
-  for (int i0 = wave * 8; i0 < np; i0 += 32) {
-    for (int j = lane; j < ncol; j += 64) {
-      double v_[8];
+  __shared__ LUShared sh;
+  // load [A | b] padded with an identity block, sixteen loads in flight
+  {
+    const int tot = np * np;
+    for (int e0 = t; e0 < tot; e0 += 256 * 16) {
+      double v_[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i0 + u;
-        if (j == np) v_[u] = (i < n && !trans) ? b[i] : 0.0;
-        else if (i < n && j < n) v_[u] = Ain[(size_t)i * n + j];
-        else v_[u] = (i == j) ? 1.0 : 0.0;
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + 256 * u;
+        const int r = e / np, c = e - r * np;
+        double val = (r == c) ? 1.0 : 0.0;
+        if (e < tot && r < n && c < n) val = Ain[(size_t)r * n + c];
+        v_[u] = val;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (i0 + u < np) M[(size_t)(i0 + u) * ld + j] = v_[u];
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < tot) {
+          const int r = e / np, c = e - r * np;
+          M[(size_t)r * ld + c] = v_[u];
+        }
+      }
     }
+    for (int r = t; r < np; r += 256) M[(size_t)r * ld + np] = (r < n && !trans) ? b[r] : 0.0;
   }
-  if (t == 0) sing = 0;
+  if (t == 0) sh.sing = 0;
   __syncthreads();
 
   for (int k0 = 0; k0 < np; k0 += LU_NB) {
     if (wave == 0) {
       double P[MR][LU_NB];
-#pragma unroll
-      for (int m = 0; m < MR; ++m) {
-        const int r = k0 + lane + 64 * m;
-#pragma unroll
-        for (int c = 0; c < LU_NB; ++c) P[m][c] = r < np ? M[(size_t)r * ld + k0 + c] : 0.0;
-      }
-      int sg = 0;
       int lpos[MR];
 #pragma unroll
       for (int m = 0; m < MR; ++m) {
         const int r = k0 + lane + 64 * m;
         lpos[m] = r < np ? r : -1;  // -1: no row (never a candidate, never updated)
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) P[m][c] = r < np ? M[(size_t)r * ld + k0 + c] : 0.0;
       }
-      // four groups of four columns: compile-time offsets inside a group,
-      // the group's columns shift to the front afterwards
-      lu_panel<MR, 0>(P, lpos, M, ld, ncol, lane, k0, spiv, sg);
-      if (sg && lane == 0) sing = 1;
+      int sg = 0;
+      lu_panel<MR, 0>(P, lpos, M, ld, lane, k0, sh, sg);
+      if (sg) {
+        if (lane == 0) sh.sing = 1;
+      } else {
+        // rows whose position changed: physical row -> final position
+        int base = 0;
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+          const int r = k0 + lane + 64 * m;
+          const bool moved = lpos[m] >= 0 && lpos[m] != r;
+          const unsigned long long mk = __ballot(moved);
+          if (moved) {
+            const int idx = base + __builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+            sh.mv_src[idx] = r;
+            sh.mv_dst[idx] = lpos[m];
+          }
+          base += __builtin_popcountll(mk);
+        }
+        if (lane == 0) sh.nmv = base;
+      }
     }
     __syncthreads();
-    if (sing) break;
-    const int j0 = k0 + LU_NB;
+    if (sh.sing) break;
+    // the panel's interchanges applied to every column (columns left of the
+    // panel hold L and only matter to the transposed solve)
+    {
+      const int nmv = sh.nmv;
+      for (int j = (trans ? 0 : k0) + t; j < ncol; j += 256) {
+        double tmp[2 * LU_NB];
+#pragma unroll
+        for (int q = 0; q < 2 * LU_NB; ++q)
+          if (q < nmv) tmp[q] = M[(size_t)sh.mv_src[q] * ld + j];
+#pragma unroll
+        for (int q = 0; q < 2 * LU_NB; ++q)
+          if (q < nmv) M[(size_t)sh.mv_dst[q] * ld + j] = tmp[q];
+      }
+    }
+    __syncthreads();
+    const int j0 = k0 + LU_NB;  // (after the last panel only the right-hand side is left of U12)
     // U12 = L11^{-1} A12: one column per thread, in registers
     for (int j = j0 + t; j < ncol; j += 256) {
       double u[LU_NB];
@@ -894,39 +913,43 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       for (int c = 1; c < LU_NB; ++c) M[(size_t)(k0 + c) * ld + j] = u[c];
     }
     __syncthreads();
-    // trailing update A22 -= L21 U12: lane -> column, wave -> pairs of rows
-    for (int jj = j0 + lane; jj < ncol; jj += 64) {
-      double u[LU_NB];
+    // A22 -= L21 U12 on the matrix cores: tile (ti, tj) of 16 x 16; operands
+    // A[i][k] = -L21 in lane i + 16 k, B[k][j] = U12 in lane j + 16 k, the
+    // tile itself as accumulator (lane l, register r: row l/16 + 4 r, column l % 16)
+    {
+      const int nt = (np - j0) / 16;
+      const int li = lane & 15, lk = lane >> 4;
+      for (int e = wave; e < nt * nt; e += 4) {
+        const int ti = e / nt, tj = e - ti * nt;
+        const int i0 = j0 + 16 * ti, c0 = j0 + 16 * tj;
+        d4 acc;
 #pragma unroll
-      for (int c = 0; c < LU_NB; ++c) u[c] = M[(size_t)(k0 + c) * ld + jj];
-      int i = j0 + 2 * wave;
-      for (; i + 1 < np; i += 8) {
-        const double* L0 = M + (size_t)i * ld + k0;
-        const double* L1 = L0 + ld;
-        double s0 = M[(size_t)i * ld + jj], s1 = M[(size_t)(i + 1) * ld + jj];
+        for (int r = 0; r < 4; ++r) acc[r] = M[(size_t)(i0 + lk + 4 * r) * ld + c0 + li];
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) {
-          s0 = fma(-L0[c], u[c], s0);
-          s1 = fma(-L1[c], u[c], s1);
+        for (int s = 0; s < 4; ++s) {
+          const double a = -M[(size_t)(i0 + li) * ld + k0 + 4 * s + lk];
+          const double bb = M[(size_t)(k0 + 4 * s + lk) * ld + c0 + li];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
         }
-        M[(size_t)i * ld + jj] = s0;
-        M[(size_t)(i + 1) * ld + jj] = s1;
-      }
-      if (i < np) {
-        const double* L0 = M + (size_t)i * ld + k0;
-        double s0 = M[(size_t)i * ld + jj];
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) s0 = fma(-L0[c], u[c], s0);
-        M[(size_t)i * ld + jj] = s0;
+        for (int r = 0; r < 4; ++r) M[(size_t)(i0 + lk + 4 * r) * ld + c0 + li] = acc[r];
+      }
+      // right-hand-side column
+      for (int i = j0 + t; i < np; i += 256) {
+        const double* Li = M + (size_t)i * ld + k0;
+        double s_ = M[(size_t)i * ld + np];
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) s_ = fma(-Li[c], M[(size_t)(k0 + c) * ld + np], s_);
+        M[(size_t)i * ld + np] = s_;
       }
     }
     __syncthreads();
   }
-  if (sing) {
+  if (sh.sing) {
     if (t == 0) flag[0] = 4;
     return;
   }
-  for (int i = t; i < n; i += 256) piv[i] = spiv[i];
+  for (int i = t; i < n; i += 256) piv[i] = sh.spiv[i];
   if (wave != 0) return;
   // wave 0: w distributed as rows lane + 64 m
   double w[MR];
@@ -941,9 +964,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
     for (int i1 = np; i1 > 0; i1 -= LU_NB) {
       const int i0 = i1 - LU_NB;
       const int mi = i0 >> 6;
-      double xb[LU_NB], dg[LU_NB], ub[MR][LU_NB];
-#pragma unroll
-      for (int cc = 0; cc < LU_NB; ++cc) dg[cc] = M[(size_t)(i0 + cc) * ld + i0 + cc];
+      double xb[LU_NB], ub[MR][LU_NB];
 #pragma unroll
       for (int m = 0; m < MR; ++m) {
         const int r = lane + 64 * m;
@@ -957,7 +978,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
         double sel = w[0];
 #pragma unroll
         for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
-        const double xi = readlane_d(sel, i & 63) / dg[cc];
+        const double xi = readlane_d(sel, i & 63) * sh.dinv[i];
         xb[cc] = xi;
 #pragma unroll
         for (int m = 0; m < MR; ++m) {
@@ -989,7 +1010,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       double sel = w[0];
 #pragma unroll
       for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
-      const double yi = readlane_d(sel, li) / M[(size_t)i * ld + i];
+      const double yi = readlane_d(sel, li) * sh.dinv[i];
 #pragma unroll
       for (int m = 0; m < MR; ++m) {
         const int r = lane + 64 * m;
@@ -1013,19 +1034,19 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
       const int r = lane + 64 * m;
-      if (r < np) wsv[r] = w[m];
+      if (r < np) sh.wsv[r] = w[m];
     }
     wave_memory_sync();
     if (lane == 0)
       for (int k = np - 1; k >= 0; --k) {
-        const int pk = spiv[k];
-        const double tmp = wsv[k]; wsv[k] = wsv[pk]; wsv[pk] = tmp;
+        const int pk = sh.spiv[k];
+        const double tmp = sh.wsv[k]; sh.wsv[k] = sh.wsv[pk]; sh.wsv[pk] = tmp;
       }
     wave_memory_sync();
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
       const int r = lane + 64 * m;
-      if (r < np) w[m] = wsv[r];
+      if (r < np) w[m] = sh.wsv[r];
     }
   }
 #pragma unroll
@@ -1036,11 +1057,13 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   if (lane == 0) flag[0] = 0;
 }
 
+// Dynamic LDS of the factorisation kernels besides the matrix.
+constexpr int kLUStaticBytes = (int)sizeof(LUShared) + 256;
+
 template <bool IN_LDS, int MR>
-__global__ __launch_bounds__(256) void lu_solve_kernel(int n, const double* __restrict__ Ain,
-                                                       const double* __restrict__ b, double* x,
-                                                       double* __restrict__ Aglob, int* piv,
-                                                       int trans, int* flag) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void lu_solve_kernel(
+    int n, const double* __restrict__ Ain, const double* __restrict__ b, double* x, double* __restrict__ Aglob,
+    int* piv, int trans, int* flag) {
   extern __shared__ double lds[];
   lu_body<IN_LDS, MR>(n, Ain, b, x, Aglob, piv, trans, flag, lds);
 }
@@ -1215,7 +1238,8 @@ __global__ __launch_bounds__(256) void batch_norms_kernel(const SolveDesc* __res
 
 // One workgroup per system: J delta = F.
 template <bool IN_LDS, int MR>
-__global__ __launch_bounds__(256) void batch_lu_kernel(const SolveDesc* __restrict__ d,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void batch_lu_kernel(
+    const SolveDesc* __restrict__ d,
                                                        const int* __restrict__ mask, int* flags) {
   extern __shared__ double lds[];
   const int b = blockIdx.x;
@@ -1350,7 +1374,7 @@ hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, dou
   const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
   // factors of [A | b], padded, in dynamic LDS when they fit
   const size_t lds_bytes = (size_t)np * (np + 1) * sizeof(double);
-  const size_t static_bytes = 256 * 4 + 256 * 8 + 64;
+  const size_t static_bytes = kLUStaticBytes;
   static int max_lds = -1;
   if (max_lds < 0) {
     int dev = 0, val = 0;
@@ -1476,7 +1500,7 @@ static void set_batch_lu_lds(int bytes) {
 hipError_t launch_batch_lu(const BatchArgs& a, int* flags, hipStream_t st) {
   const int np = a.max_np;
   const size_t lds_bytes = (size_t)np * (np + 1) * sizeof(double);
-  const size_t static_bytes = 256 * 4 + 256 * 8 + 64;
+  const size_t static_bytes = kLUStaticBytes;
   static int max_lds = -1;
   if (max_lds < 0) {
     int dev = 0, val = 0;
