@@ -8,9 +8,9 @@ J Delta = F, and the residual at c - Delta.  value = Newton-matrix entries
 (n^2 = 128^2) per second of step time.
 
 Beside it: seconds per Newton solve at N = 64, the 256-problem family solved
-batched against the plain path per problem, and the implicit-function gradient
-against finite differences of re-solves (each on the same GPU, at equal
-convergence).
+batched against the plain path per problem, the implicit-function gradient
+against finite differences of re-solves, and the mixed-precision Newton matrix
+against FP64 at N = 128 (each on the same GPU, at equal convergence).
 
 Prints one JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
@@ -170,6 +170,47 @@ def bench_adjoint(dse, workloads, torch) -> dict:
             "dL_dG0": {"ift": dG0, "fd": fd_g, "rel_diff": abs(dG0 - fd_g) / abs(fd_g)}}
 
 
+def bench_mixed(dse, workloads, torch) -> dict:
+    """N = 128 per function, 1024+256 radial x 128 angular: the Newton matrix
+    with FP32 derivative sums and FP32 MFMA contraction against FP64 (device
+    time per assembly, J error against the FP64 matrix), and the Newton solve in
+    both precisions (F and the LU in FP64 throughout): iterations, time, and the
+    largest per-coefficient difference of the two roots."""
+    cfg = workloads.config("cfg3")
+    out = {"workload": workloads.WORKLOAD_NAMES["cfg3"]}
+    solvers = {"fp64": dse.Solver(**cfg), "mixed": dse.Solver(**dict(cfg, precision=1))}
+    c0 = solvers["fp64"].start_guess()
+    Js = {}
+    for k, s in solvers.items():
+        J, _ = s.jacobian(c0)
+        Js[k] = J
+        s.set_timing(True)
+        for _ in range(10):
+            s.jacobian(c0)
+        st, _ = s.read_timings()
+        s.set_timing(False)
+        out["assembly_ms_" + k] = sum(st)
+        out["stage_ms_" + k] = st
+    d = Js["mixed"] - Js["fp64"]
+    out["J_normwise_rel_err"] = float(d.norm() / Js["fp64"].norm())
+    out["J_worst_row_rel_err"] = float((d.abs().amax(dim=1) / Js["fp64"].abs().amax(dim=1)).max())
+    roots = {}
+    for k, s in solvers.items():
+        s.newton(extra_iters=8)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.newton(extra_iters=8)
+        torch.cuda.synchronize()
+        out["newton_s_" + k] = time.perf_counter() - t0
+        out["newton_iters_" + k] = r.iters
+        out["newton_status_" + k] = r.status
+        roots[k] = r.c
+    dc = (roots["mixed"] - roots["fp64"]).abs()
+    out["root_max_abs_diff"] = float(dc.max())
+    out["root_max_rel_diff"] = float(dc.max() / roots["fp64"].abs().max())
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +295,7 @@ def main() -> int:
     if not args.no_extras:
         out["batched"] = bench_batched(dse, workloads, torch)
         out["adjoint"] = bench_adjoint(dse, workloads, torch)
+        out["mixed"] = bench_mixed(dse, workloads, torch)
     if not args.no_cpu:
         cb = cpu_baseline(cfg, c.cpu().numpy())
         cb["gpu_speedup"] = value / cb["value"]

@@ -117,7 +117,7 @@ dse_status set_launch(dse_batch* B, int slices, int grid, int order) {
   B->order = order;
   struct It { double cost; int4 w; };
   std::vector<It> its;
-  int max_nj = 16, max_n = 1, max_rbt = 1;
+  int max_nj = 16, max_n = 1, max_rbt = 1, max_dress = 1;
   for (int b = 0; b < B->count; ++b) {
     dse::Views& v = B->desc[b].v;
     v.KS = slices;
@@ -131,6 +131,7 @@ dse_status set_launch(dse_batch* B, int slices, int grid, int order) {
     max_nj = std::max(max_nj, v.NJ);
     max_n = std::max(max_n, v.n);
     max_rbt = std::max(max_rbt, v.Rbp / 16 + (v.RG + 15) / 16);
+    max_dress = std::max(max_dress, (v.Qp + v.n + 255) / 256);
   }
   if (order == 1)
     std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
@@ -149,6 +150,7 @@ dse_status set_launch(dse_batch* B, int slices, int grid, int order) {
   B->args.max_np = (max_n + 15) / 16 * 16;
   B->args.max_nj = max_nj;
   B->args.max_rbt = max_rbt;
+  B->args.max_dress_blocks = max_dress;
   return DSE_OK;
 }
 
@@ -222,6 +224,10 @@ dse_status dse_batch_init(const dse_params* p, int32_t count, void* d_workspace,
     char e[512];
     if (dse::validate(&p[b], e) != DSE_OK) {
       set_err(g_batch_err, "problem %d: %s", b, e);
+      return DSE_E_INVALID;
+    }
+    if (p[b].precision != DSE_FP64) {
+      set_err(g_batch_err, "problem %d: the batched family runs in FP64 (precision must be DSE_FP64)", b);
       return DSE_E_INVALID;
     }
     cap = std::min(cap, slices_cap(p[b]));

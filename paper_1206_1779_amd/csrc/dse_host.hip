@@ -220,7 +220,10 @@ size_t layout(const dse_params& p, Views* v, char* base, int ks) {
   t.lnZy = (double*)take(t.Qp * d);
   t.lnGy = (double*)take(t.Qp * d);
   t.Ttab = (double*)take((size_t)t.Qp * t.NJ * d);
+  t.Ttab32 = (float*)take((size_t)t.Qp * t.NJ * sizeof(float));
   t.Text = (double*)take((size_t)t.n * t.NJ * d);
+  t.TtabT = (double*)take((size_t)t.Qp * t.NJ * d);
+  t.TextT = (double*)take((size_t)t.n * t.NJ * d);
   t.xrow = (double*)take((t.RZ + t.RG) * d);
   t.lnX = (double*)take(t.n * d);
   t.ang = (double*)take(5 * t.Kp * d);
@@ -273,6 +276,8 @@ dse_status upload_tables(const dse_params& p, const Views& v, const Phys& ph, hi
   }
   std::vector<double> Ttab((size_t)v.Qp * NJ);
   for (int i = 0; i < v.Qp; ++i) cheb_row(sq[i], NJ, &Ttab[(size_t)i * NJ]);
+  std::vector<float> Ttab32(Ttab.size());
+  for (size_t i = 0; i < Ttab.size(); ++i) Ttab32[i] = (float)Ttab[i];
 
   std::vector<double> Text((size_t)v.n * NJ), xrow(v.RZ + v.RG);
   for (int r = 0; r < v.n; ++r) {
@@ -284,6 +289,11 @@ dse_status upload_tables(const dse_params& p, const Views& v, const Phys& ph, hi
     const double x = exp(ph.L0 + L1 * s);
     xrow[gl ? i : v.RZ + i] = x;
   }
+  std::vector<double> TtabT(Ttab.size()), TextT(Text.size());
+  for (int i = 0; i < v.Qp; ++i)
+    for (int j = 0; j < NJ; ++j) TtabT[(size_t)j * v.Qp + i] = Ttab[(size_t)i * NJ + j];
+  for (int r = 0; r < v.n; ++r)
+    for (int j = 0; j < NJ; ++j) TextT[(size_t)j * v.n + r] = Text[(size_t)r * NJ + j];
   xrow[v.RZ - 1] = p.lambda2;         // gluon subtraction point x_Z = Lambda^2
   xrow[v.RZ + v.RG - 1] = 0.0;        // ghost subtraction point x_G = 0
 
@@ -308,7 +318,10 @@ dse_status upload_tables(const dse_params& p, const Views& v, const Phys& ph, hi
       {v.y, y.data(), v.Qp * 8u},
       {v.W, W.data(), v.Qp * 8u},
       {v.Ttab, Ttab.data(), Ttab.size() * 8},
+      {v.Ttab32, Ttab32.data(), Ttab32.size() * 4},
       {v.Text, Text.data(), Text.size() * 8},
+      {v.TtabT, TtabT.data(), TtabT.size() * 8},
+      {v.TextT, TextT.data(), TextT.size() * 8},
       {v.xrow, xrow.data(), xrow.size() * 8},
       {v.ang, ang.data(), ang.size() * 8},
       // the padding rows of B must be finite (they only feed padding rows of Eq)
@@ -376,7 +389,7 @@ struct DeviceGuard {
 dse_status eval_residual(dse_ctx* ctx, const double* c, double* F, double* S) {
   const dse::Views& v = ctx->v;
   HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, c, ctx->st));
-  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, 0, ctx->st, nullptr));
+  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, 0, false, ctx->st, nullptr));
   HIP_TRY(ctx, dse::launch_residual_rows(v, ctx->ph, F, S, ctx->st));
   return DSE_OK;
 }
@@ -395,10 +408,11 @@ dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, do
   }
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[0], ctx->st));
   HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, c, ctx->st));
-  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, 1, ctx->st, ev ? ev + 1 : nullptr));
-  HIP_TRY(ctx, dse::launch_contract(v, ctx->st));
+  const bool mix = ctx->p.precision == DSE_MIXED;
+  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, 1, mix, ctx->st, ev ? ev + 1 : nullptr));
+  HIP_TRY(ctx, dse::launch_contract(v, mix, ctx->st));
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[4], ctx->st));
-  HIP_TRY(ctx, dse::launch_assemble(v, ctx->ph, J, F, S, ctx->st));
+  HIP_TRY(ctx, dse::launch_assemble(v, ctx->ph, J, F, S, mix, ctx->st));
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[5], ctx->st));
   return DSE_OK;
 }
@@ -608,8 +622,8 @@ dse_status dse_vjp(dse_ctx* ctx, const double* d_c, const double* d_u, double* d
   const dse::Views& v = ctx->v;
   HIP_TRY(ctx, dse::launch_row_weights(v, d_u, ctx->st));
   HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, d_c, ctx->st));
-  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, d_uJ ? 2 : 3, ctx->st, nullptr));
-  if (d_uJ) HIP_TRY(ctx, dse::launch_contract(v, ctx->st));
+  HIP_TRY(ctx, dse::launch_points(v, ctx->ph, d_uJ ? 2 : 3, false, ctx->st, nullptr));
+  if (d_uJ) HIP_TRY(ctx, dse::launch_contract(v, false, ctx->st));
   HIP_TRY(ctx, dse::launch_vjp_reduce(v, d_u, d_uJ, d_utheta, ctx->st));
   return DSE_OK;
 }

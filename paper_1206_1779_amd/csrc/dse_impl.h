@@ -56,11 +56,15 @@ struct Views {
   double* lnZy;          // [Qp] ln Z at the radial nodes
   double* lnGy;          // [Qp]
   double* Ttab;          // [Qp][NJ] Tilde-T_j(s(y_q))
+  float* Ttab32;         // [Qp][NJ] the same in FP32 (mixed-precision contraction)
+  double* TtabT;         // [NJ][Qp] transposed (dressing GEMV)
   double* Text;          // [n][NJ]  Tilde-T_j(s(x_r)) at the collocation points
+  double* TextT;         // [NJ][n]  transposed
   double* xrow;          // [RZ + RG] external momentum of each row
   double* lnX;           // [n] ln Z (gluon rows) / ln G (ghost rows) at x_r
   double* ang;           // [5][Kp] cos, sin^2(theta/2), v sin^2, v sin^4, sin^2
   // per assembly
+  // (in mixed precision Bm, Dp, Eq and Dgh hold FP32 values at the same indices)
   double* Bm;            // [KS][Rbp][Qp] angular sums per slice: rows gluon-a | gluon-b | ghost-b
   double* Dp;            // [3][RZ or RG][nqt*KS][NJ] k-side partials: gluon-a | gluon-b | ghost-a
   double* Pip;           // [RZ + RG][nqt*KS][2] partial self-energies (sum, rounding error)
@@ -102,14 +106,15 @@ void start_guess_host(const dse_params& p, const Phys& ph, double* c_out);
 
 // Kernel launchers (dse_kernels.hip).  All enqueue on `st`.
 hipError_t launch_dressing(const Views& v, const Phys& ph, const double* c, hipStream_t st);
-// mode: 0 residual, 1 Jacobian, 2 vector-Jacobian product, 3 parameter VJP
-hipError_t launch_points(const Views& v, const Phys& ph, int mode, hipStream_t st,
+// mode: 0 residual, 1 Jacobian, 2 vector-Jacobian product, 3 parameter VJP;
+// mix (Jacobian mode only): derivative sums in FP32
+hipError_t launch_points(const Views& v, const Phys& ph, int mode, bool mix, hipStream_t st,
                          hipEvent_t* ev /* nullable: [3] events before, between and after the
                                            gluon and ghost point kernels */);
-hipError_t launch_contract(const Views& v, hipStream_t st);
+hipError_t launch_contract(const Views& v, bool mix, hipStream_t st);
 hipError_t launch_row_weights(const Views& v, const double* u, hipStream_t st);
 hipError_t launch_vjp_reduce(const Views& v, const double* u, double* uJ, double* uth, hipStream_t st);
-hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S,
+hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S, bool mix,
                            hipStream_t st);
 hipError_t launch_residual_rows(const Views& v, const Phys& ph, double* F, double* S,
                                 hipStream_t st);
@@ -128,6 +133,7 @@ struct BatchArgs {
   int count;
   const int* mask;        // [count] nonzero: problem takes part
   int max_n, max_np, max_nj, max_rbt;  // largest n, padded n, padded order, contraction row blocks
+  int max_dress_blocks;                // dressing blocks per problem (largest Qp + n over 256)
 };
 hipError_t launch_batch_dressing(const BatchArgs& a, const double* cpk, int which, int* counter,
                                  hipStream_t st);

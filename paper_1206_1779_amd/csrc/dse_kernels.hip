@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "dse_impl.h"
@@ -69,7 +70,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // --------------------------------------------------------------------------
 // dressing: coef (c_0 halved, zero padded), ln Z / ln G at radial nodes and at
 // the collocation points.
-__device__ __forceinline__ void dressing_body(const Views& v, const Phys& ph, const double* __restrict__ c) {
+// Outputs o0 + t, o0 + t + ostep, ... of [radial nodes | collocation points];
+// the block with write_coef also stores the coefficient vector.  Tables are
+// read transposed (j-major), so consecutive threads read consecutive words.
+__device__ __forceinline__ void dressing_body(const Views& v, const Phys& ph, const double* __restrict__ c,
+                                              int o0, int ostep, bool write_coef) {
   __shared__ double sa[DSE_MAX_N], sb[DSE_MAX_N];
   const int t = threadIdx.x;
   const int NJ = v.NJ;
@@ -80,16 +85,23 @@ __device__ __forceinline__ void dressing_body(const Views& v, const Phys& ph, co
     // the table holds Tilde-T_0 = 1/2: keep the unhalved value for the GEMV
     sa[j] = j < v.n_z ? c[j] : 0.0;
     sb[j] = j < v.n_g ? c[v.n_z + j] : 0.0;
-    v.coef[j] = a;
-    v.coef[NJ + j] = b;
+    if (write_coef) {
+      v.coef[j] = a;
+      v.coef[NJ + j] = b;
+    }
   }
   __syncthreads();
   const int nout = v.Qp + v.n;
-  for (int o = t; o < nout; o += 256) {
+  for (int o = o0 + t; o < nout; o += ostep) {
     if (o < v.Qp) {
-      const double* T = v.Ttab + (size_t)o * NJ;
+      const double* T = v.TtabT + o;
       double z = 0.0, g = 0.0;
-      for (int j = 0; j < NJ; ++j) { z = fma(sa[j], T[j], z); g = fma(sb[j], T[j], g); }
+#pragma unroll 8
+      for (int j = 0; j < NJ; ++j) {
+        const double tj = T[(size_t)j * v.Qp];
+        z = fma(sa[j], tj, z);
+        g = fma(sb[j], tj, g);
+      }
       double ly = log(v.y[o]);
       if (ly < ph.ln_eps2) {
         z += 2.0 * ph.kappa * (ly - ph.ln_eps2);
@@ -103,17 +115,18 @@ __device__ __forceinline__ void dressing_body(const Views& v, const Phys& ph, co
       v.lnGy[o] = g;
     } else {
       int r = o - v.Qp;
-      const double* T = v.Text + (size_t)r * NJ;
+      const double* T = v.TextT + r;
       const double* cc = r < v.n_z ? sa : sb;
       double s = 0.0;
-      for (int j = 0; j < NJ; ++j) s = fma(cc[j], T[j], s);
+#pragma unroll 8
+      for (int j = 0; j < NJ; ++j) s = fma(cc[j], T[(size_t)j * v.n], s);
       v.lnX[r] = s;  // collocation points lie in [eps2, lambda2]: no extension
     }
   }
 }
 
 __global__ __launch_bounds__(256) void dressing_kernel(Views v, Phys ph, const double* __restrict__ c) {
-  dressing_body(v, ph, c);
+  dressing_body(v, ph, c, blockIdx.x * 256, gridDim.x * 256, blockIdx.x == 0);
 }
 
 // --------------------------------------------------------------------------
@@ -131,32 +144,32 @@ __host__ __device__ constexpr int slice_count() {
   return c;
 }
 
-template <int CNT, int O>
-__device__ __forceinline__ void slice_stage(double* vals, int lane, int& base, bool& writer) {
+template <int CNT, int O, typename T>
+__device__ __forceinline__ void slice_stage(T* vals, int lane, int& base, bool& writer) {
   if constexpr (O < 64) {
     if constexpr (CNT % 2 == 0) {
       constexpr int H = CNT / 2;
       const bool hi = (lane & O) != 0;
 #pragma unroll
       for (int i = 0; i < H; ++i) {
-        const double send = hi ? vals[i] : vals[i + H];
-        const double keep = hi ? vals[i + H] : vals[i];
+        const T send = hi ? vals[i] : vals[i + H];
+        const T keep = hi ? vals[i + H] : vals[i];
         vals[i] = keep + __shfl_xor(send, O, 64);
       }
       if (hi) base += H;
-      slice_stage<H, O * 2>(vals, lane, base, writer);
+      slice_stage<H, O * 2, T>(vals, lane, base, writer);
     } else {
 #pragma unroll
       for (int i = 0; i < CNT; ++i) vals[i] += __shfl_xor(vals[i], O, 64);
       if (lane & O) writer = false;
-      slice_stage<CNT, O * 2>(vals, lane, base, writer);
+      slice_stage<CNT, O * 2, T>(vals, lane, base, writer);
     }
   }
 }
 
-template <int NV, int G>
-__device__ __forceinline__ void slice_reduce(double* vals, int lane, int& base, bool& writer) {
-  slice_stage<NV, G>(vals, lane, base, writer);
+template <int NV, int G, typename T>
+__device__ __forceinline__ void slice_reduce(T* vals, int lane, int& base, bool& writer) {
+  slice_stage<NV, G, T>(vals, lane, base, writer);
 }
 
 // --------------------------------------------------------------------------
@@ -172,6 +185,8 @@ __device__ __forceinline__ void slice_reduce(double* vals, int lane, int& base, 
 // the row weight rw[row]: B and D then sum to u^T dF/dc; the pair slots of
 // Pip carry d Pi / d alpha, weighted); 3 parameter VJP only (weighted
 // d Pi / d alpha, no B, no D).
+// MIX (Jacobian mode): the derivative sums B and D, and the k-side
+// recurrence, in FP32; every quantity that enters F stays FP64.
 enum { MODE_RES = 0, MODE_JAC = 1, MODE_VJP = 2, MODE_VTH = 3 };
 
 // LDS of one point-kernel block (doubles): red[3][4] at 0, bs[2][4][64] at 16,
@@ -179,10 +194,11 @@ enum { MODE_RES = 0, MODE_JAC = 1, MODE_VJP = 2, MODE_VTH = 3 };
 template <int NJ>
 __host__ __device__ constexpr int point_smem() { return 528 + 8 * NJ; }
 
-template <int KIND, int NJ, int MODE>
+template <int KIND, int NJ, int MODE, bool MIX = false>
 __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int row, int tile,
                                            double* __restrict__ smem) {
   using TL = Tile<KIND, NJ>;
+  using acc_t = typename std::conditional<MIX, float, double>::type;
   constexpr int G = TL::G;
   constexpr int JT = TL::JT;
   constexpr int NT = KIND == GLUON ? 2 : 1;  // k-side targets
@@ -231,11 +247,12 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   const int Kp = v.Kp;
   const double rw = WEIGHTED ? v.rw[growrow] : 1.0;
 
-  double pi_s = 0.0, pi_c = 0.0, abs_acc = 0.0, Ba = 0.0, Bb = 0.0;
-  double Da[JAC ? JT : 1], Db[JAC && NT == 2 ? JT : 1];
+  double pi_s = 0.0, pi_c = 0.0, abs_acc = 0.0;
+  acc_t Ba = 0, Bb = 0;
+  acc_t Da[JAC ? JT : 1], Db[JAC && NT == 2 ? JT : 1];
   if (JAC) {
 #pragma unroll
-    for (int jj = 0; jj < JT; ++jj) { Da[jj] = 0.0; if (NT == 2) Db[jj] = 0.0; }
+    for (int jj = 0; jj < JT; ++jj) { Da[jj] = 0; if (NT == 2) Db[jj] = 0; }
   }
   const int member = lane & (G - 1);
 
@@ -305,7 +322,7 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
         two_sum_add(pi_s, pi_c, tq + tm);
         abs_acc += fabs(tq) + fabs(tm);
       }
-      if (JAC) { Ba += Pa; Bb += Pb; }
+      if (JAC) { Ba += (acc_t)Pa; Bb += (acc_t)Pb; }
     } else {
       double val = pref * wk * exp(lGy + lZz - 2.0 * lz);  // rho G(y) Z(z) / z^2
       if (WEIGHTED) {
@@ -318,38 +335,40 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
       }
       Pa = val;                  // k-side: d / d ln Z(z)
       Pb = val;
-      if (JAC) Bb += val;        // q-side: d / d ln G(y)
+      if (JAC) Bb += (acc_t)val; // q-side: d / d ln G(y)
     }
 
     if (JAC) {
       // ---- pass 2: k-side accumulation over the G points of the lane group
+      const acc_t sA = (acc_t)s, PaA = (acc_t)Pa, PbA = (acc_t)Pb;
 #pragma unroll
       for (int r = 0; r < G; ++r) {
-        double tp, tc, pa, pb;
+        acc_t tp, tc, pa, pb;
         if (r == 0) {
-          tp = stp[0]; tc = stc[0];
+          double tp_ = stp[0], tc_ = stc[0];
 #pragma unroll
-          for (int m = 1; m < G; ++m) if (member == m) { tp = stp[m]; tc = stc[m]; }
-          pa = Pa; pb = Pb;
+          for (int m = 1; m < G; ++m) if (member == m) { tp_ = stp[m]; tc_ = stc[m]; }
+          tp = (acc_t)tp_; tc = (acc_t)tc_;
+          pa = PaA; pb = PbA;
         } else {
           // send the start pair the reading lane (member ^ r) needs
           const int want = member ^ r;
           double sp = stp[0], sc = stc[0];
 #pragma unroll
           for (int m = 1; m < G; ++m) if (want == m) { sp = stp[m]; sc = stc[m]; }
-          tp = __shfl_xor(sp, r, 64);
-          tc = __shfl_xor(sc, r, 64);
-          pa = __shfl_xor(Pa, r, 64);
-          pb = NT == 2 ? __shfl_xor(Pb, r, 64) : 0.0;
+          tp = __shfl_xor((acc_t)sp, r, 64);
+          tc = __shfl_xor((acc_t)sc, r, 64);
+          pa = __shfl_xor(PaA, r, 64);
+          pb = NT == 2 ? __shfl_xor(PbA, r, 64) : (acc_t)0;
         }
         // the owner's mapped momentum drives its recurrence
-        const double sr = r == 0 ? s : __shfl_xor(s, r, 64);
-        const double sr2 = sr + sr;
+        const acc_t sr = r == 0 ? sA : __shfl_xor(sA, r, 64);
+        const acc_t sr2 = sr + sr;
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj) {
           Da[jj] = fma(pa, tc, Da[jj]);
           if (NT == 2) Db[jj] = fma(pb, tc, Db[jj]);
-          const double tn = fma(sr2, tc, -tp);
+          const acc_t tn = fma(sr2, tc, -tp);
           tp = tc;
           tc = tn;
         }
@@ -377,14 +396,14 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   if (!JAC) return;
 
   // ---- q-side: angular sums staged in LDS, reduced over the four waves
-  double (*bs)[4][64] = reinterpret_cast<double (*)[4][64]>(smem + 16);
+  acc_t (*bs)[4][64] = reinterpret_cast<acc_t (*)[4][64]>(smem + 16);
   bs[0][wave][lane] = Ba;
   bs[1][wave][lane] = Bb;
   // ---- k-side: reduce-scatter over the lanes that hold the same slice, then
   // over the waves through LDS
-  double (*ds)[NT * NJ] = reinterpret_cast<double (*)[NT * NJ]>(smem + 528);
+  acc_t (*ds)[NT * NJ] = reinterpret_cast<acc_t (*)[NT * NJ]>(smem + 528);
   {
-    double vals[NT * JT];
+    acc_t vals[NT * JT];
 #pragma unroll
     for (int jj = 0; jj < JT; ++jj) {
       vals[jj] = Da[jj];
@@ -392,7 +411,7 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     }
     int base = 0;        // index (within this lane's NT*JT values) of vals[0]
     bool writer = true;  // one lane of each group of equal partial sums writes
-    slice_reduce<NT * JT, G>(vals, lane, base, writer);
+    slice_reduce<NT * JT, G, acc_t>(vals, lane, base, writer);
     constexpr int CNT = slice_count<NT * JT, G>();
     if (writer) {
 #pragma unroll
@@ -405,9 +424,9 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   }
   __syncthreads();
   if (t < 64) {
-    const double sa_ = ((bs[0][0][t] + bs[0][1][t]) + bs[0][2][t]) + bs[0][3][t];
-    const double sb_ = ((bs[1][0][t] + bs[1][1][t]) + bs[1][2][t]) + bs[1][3][t];
-    double* Bk = v.Bm + (size_t)ks * v.Rbp * v.Qp;
+    const acc_t sa_ = ((bs[0][0][t] + bs[0][1][t]) + bs[0][2][t]) + bs[0][3][t];
+    const acc_t sb_ = ((bs[1][0][t] + bs[1][1][t]) + bs[1][2][t]) + bs[1][3][t];
+    acc_t* Bk = reinterpret_cast<acc_t*>(v.Bm) + (size_t)ks * v.Rbp * v.Qp;
     if (KIND == GLUON) {
       Bk[(size_t)row * v.Qp + qt * 64 + t] = sa_;
       Bk[(size_t)(v.RZ + row) * v.Qp + qt * 64 + t] = sb_;
@@ -417,21 +436,21 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   }
   for (int o = t; o < NT * NJ; o += 256) {
     const int tg = o / NJ, j = o - tg * NJ;
-    double sum = ((ds[0][o] + ds[1][o]) + ds[2][o]) + ds[3][o];
-    if (j == 0) sum *= 0.5;  // Tilde-T_0 = 1/2
+    acc_t sum = ((ds[0][o] + ds[1][o]) + ds[2][o]) + ds[3][o];
+    if (j == 0) sum *= (acc_t)0.5;  // Tilde-T_0 = 1/2
     const int grp = KIND == GLUON ? tg : 2;
     const size_t base = (size_t)grp * v.RZ * ntile * NJ;
-    v.Dp[base + ((size_t)row * ntile + tile) * NJ + j] = sum;
+    reinterpret_cast<acc_t*>(v.Dp)[base + ((size_t)row * ntile + tile) * NJ + j] = sum;
   }
 }
 
 // One block per (row, tile): blockIdx.x = row * (nqt KS) + tile.
-template <int KIND, int NJ, int MODE>
+template <int KIND, int NJ, int MODE, bool MIX>
 __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
   __shared__ double smem[point_smem<NJ>()];
   const int ntile = v.nqt * v.KS;
   const int row = blockIdx.x / ntile;
-  point_body<KIND, NJ, MODE>(v, ph, row, blockIdx.x - row * ntile, smem);
+  point_body<KIND, NJ, MODE, MIX>(v, ph, row, blockIdx.x - row * ntile, smem);
 }
 
 // --------------------------------------------------------------------------
@@ -440,23 +459,27 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
 // the radial sum and meet in LDS) and add, for gluon rows, the k-side partial
 // sums of the same target; the remaining blocks reduce the ghost rows'
 // k-side partials into Dgh.  Every sum runs in a fixed order.
+template <bool MIX>
 __device__ __forceinline__ void contract_body(const Views& v, int bx, int by) {
+  using acc_t = typename std::conditional<MIX, float, double>::type;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int Qp = v.Qp, NJ = v.NJ;
   const int ntile = v.nqt * v.KS;
   const size_t dstride = (size_t)ntile * NJ;
   const int ntiles_r = v.Rbp / 16;
+  const acc_t* __restrict__ Dp = reinterpret_cast<const acc_t*>(v.Dp);
   if (bx >= ntiles_r) {
     // ghost rows, k-side (target a): Dgh[row][j] = sum over tiles
     const int row0 = (bx - ntiles_r) * 16;
-    const double* D = v.Dp + (size_t)2 * v.RZ * dstride;
+    const acc_t* D = Dp + (size_t)2 * v.RZ * dstride;
     for (int e = t; e < 16 * 16; e += 256) {
       const int r = row0 + (e >> 4), j = by * 16 + (e & 15);
       if (r < v.RG) {
-        const double* src = D + (size_t)r * dstride + j;
-        double sum = 0.0;
+        const acc_t* src = D + (size_t)r * dstride + j;
+        acc_t sum = 0;
+#pragma unroll 4
         for (int k = 0; k < ntile; ++k) sum += src[(size_t)k * NJ];
-        v.Dgh[(size_t)r * NJ + j] = sum;
+        reinterpret_cast<acc_t*>(v.Dgh)[(size_t)r * NJ + j] = sum;
       }
     }
     return;
@@ -465,82 +488,110 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by) {
   const int qper = Qp / 4;
   const int qbeg = wave * qper;
   const int i = lane & 15, kk = lane >> 4;
-  typedef double d4 __attribute__((ext_vector_type(4)));
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-  const double* A = v.Bm + (size_t)(r0 + i) * Qp + kk;
+  const acc_t* A = reinterpret_cast<const acc_t*>(v.Bm) + (size_t)(r0 + i) * Qp + kk;
   const size_t kstride = (size_t)v.Rbp * Qp;  // angular slices of B
-  const double* B = v.Ttab + (size_t)kk * NJ + j0 + i;
-  for (int q = qbeg; q < qbeg + qper; q += 4) {
-    double a = A[q];
-    for (int k = 1; k < v.KS; ++k) a += A[k * kstride + q];
-    const double b = B[(size_t)q * NJ];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-  __shared__ double part[4][4][64];
+  __shared__ acc_t part[4][4][64];
+  if constexpr (MIX) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float* B = v.Ttab32 + (size_t)kk * NJ + j0 + i;
+#pragma unroll 4
+    for (int q = qbeg; q < qbeg + qper; q += 4) {
+      float a = A[q];
+      for (int k = 1; k < v.KS; ++k) a += A[k * kstride + q];
+      const float b = B[(size_t)q * NJ];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
+    for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
+  } else {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const double* B = v.Ttab + (size_t)kk * NJ + j0 + i;
+#pragma unroll 4
+    for (int q = qbeg; q < qbeg + qper; q += 4) {
+      double a = A[q];
+      for (int k = 1; k < v.KS; ++k) a += A[k * kstride + q];
+      const double b = B[(size_t)q * NJ];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
+  }
   __syncthreads();
   {
-    // one output element per thread: (ri, cj) of the tile; the MFMA result
-    // D[ri][cj] sits in lane (ri % 4) * 16 + cj, register ri / 4
-    // (v_mfma_f64_16x16x4f64: lane l, register r holds D[l/16 + 4 r][l % 16])
+    // one output element per thread: (ri, cj) of the tile.  Result layouts:
+    // v_mfma_f64_16x16x4f64, lane l, register r: D[l/16 + 4 r][l % 16];
+    // v_mfma_f32_16x16x4f32, lane l, register r: D[4 (l/16) + r][l % 16]
     const int ri = t >> 4, cj = t & 15;
-    const int l = (ri & 3) * 16 + cj, rg = ri >> 2;
-    double sum = ((part[0][rg][l] + part[1][rg][l]) + part[2][rg][l]) + part[3][rg][l];
+    const int l = MIX ? (ri >> 2) * 16 + cj : (ri & 3) * 16 + cj;
+    const int rg = MIX ? (ri & 3) : (ri >> 2);
+    acc_t sum = ((part[0][rg][l] + part[1][rg][l]) + part[2][rg][l]) + part[3][rg][l];
     const int row = r0 + ri, col = j0 + cj;
     if (row < 2 * v.RZ) {  // gluon rows: add the k-side sums of the same target
-      const double* src = v.Dp + (size_t)row * dstride + col;  // groups a, b are contiguous
-      double ds_ = 0.0;
+      const acc_t* src = Dp + (size_t)row * dstride + col;  // groups a, b are contiguous
+      acc_t ds_ = 0;
+#pragma unroll 4
       for (int k = 0; k < ntile; ++k) ds_ += src[(size_t)k * NJ];
       sum += ds_;
     }
-    v.Eq[(size_t)row * NJ + col] = sum;
+    reinterpret_cast<acc_t*>(v.Eq)[(size_t)row * NJ + col] = sum;
   }
 }
 
-__global__ __launch_bounds__(256) void contract_kernel(Views v) { contract_body(v, blockIdx.x, blockIdx.y); }
+template <bool MIX>
+__global__ __launch_bounds__(256) void contract_kernel(Views v) { contract_body<MIX>(v, blockIdx.x, blockIdx.y); }
+
 
 // --------------------------------------------------------------------------
-// helpers for assembly: partial sums over the radial tiles, in tile order
-__device__ __forceinline__ double sum_tiles(const double* p, int nqt) {
-  double s = 0.0;
-  for (int i = 0; i < nqt; ++i) s += p[i];
-  return s;
-}
-
-
-// Self-energy of one row from its (sum, error) tile pairs.
-__device__ __forceinline__ double pi_row(const double* p, int nqt) {
-  double s = 0.0, c = 0.0;
-  for (int i = 0; i < nqt; ++i) { two_sum_add(s, c, p[2 * i]); c += p[2 * i + 1]; }
-  return s + c;
-}
-
-// F_r and S_r for one row (Sec. 3: z(x_i) and g(x_i) with MOM subtraction).
-__device__ __forceinline__ void row_residual(const Views& v, const Phys& ph, int r, double* F,
-                                             double* S) {
+// F_r and S_r for one row (Sec. 3: z(x_i) and g(x_i) with MOM subtraction),
+// by one wave: lane k takes the partial tiles k, k + 64, ... of the row and of
+// its subtraction row (compensated sums of the (sum, error) pairs), then a
+// fixed-order wave reduction.
+__device__ __forceinline__ void row_residual_wave(const Views& v, const Phys& ph, int r, double* F,
+                                                  double* S, int lane) {
   const bool gl = r < v.n_z;
   const int rr = gl ? r : v.RZ + (r - v.n_z);          // row in xrow / Pip
   const int sub = gl ? v.RZ - 1 : v.RZ + v.RG - 1;      // subtraction row
   const int nt = v.nqt * v.KS;
-  const double pix = pi_row(v.Pip + (size_t)2 * rr * nt, nt);
-  const double pis = pi_row(v.Pip + (size_t)2 * sub * nt, nt);
-  const double abx = sum_tiles(v.Absp + (size_t)rr * nt, nt);
-  const double abs_ = sum_tiles(v.Absp + (size_t)sub * nt, nt);
-  const double d = exp(-v.lnX[r]);
-  const double par = gl ? ph.z_lambda_inv : ph.g0_inv;
-  F[r] = d - par - pix + pis;
-  if (S) S[r] = fabs(d) + fabs(par) + abx + abs_;
+  const double* __restrict__ px = v.Pip + (size_t)2 * rr * nt;
+  const double* __restrict__ ps = v.Pip + (size_t)2 * sub * nt;
+  const double* __restrict__ ax_ = v.Absp + (size_t)rr * nt;
+  const double* __restrict__ as_ = v.Absp + (size_t)sub * nt;
+  double xs = 0.0, xc = 0.0, ss = 0.0, sc = 0.0, ax = 0.0, as = 0.0;
+  for (int k = lane; k < nt; k += 64) {
+    two_sum_add(xs, xc, px[2 * k]);
+    xc += px[2 * k + 1];
+    two_sum_add(ss, sc, ps[2 * k]);
+    sc += ps[2 * k + 1];
+    ax += ax_[k];
+    as += as_[k];
+  }
+  wave_sum2(xs, xc);
+  wave_sum2(ss, sc);
+  ax = wave_sum(ax);
+  as = wave_sum(as);
+  if (lane == 0) {
+    const double d = exp(-v.lnX[r]);
+    const double par = gl ? ph.z_lambda_inv : ph.g0_inv;
+    F[r] = d - par - (xs + xc) + (ss + sc);
+    if (S) S[r] = fabs(d) + fabs(par) + ax + as;
+  }
 }
 
+// one wave per row
 __global__ __launch_bounds__(256) void residual_rows_kernel(Views v, Phys ph, double* F, double* S) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < v.n) row_residual(v, ph, r, F, S);
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r < v.n) row_residual_wave(v, ph, r, F, S, threadIdx.x & 63);
 }
 
-// J row r = one block.
+// J row r = one block.  MIX: Eq and Dgh hold FP32 sums.
+template <bool MIX>
 __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, int r, double* __restrict__ J,
                                               double* F, double* S) {
+  using acc_t = typename std::conditional<MIX, float, double>::type;
+  const acc_t* __restrict__ Eq = reinterpret_cast<const acc_t*>(v.Eq);
+  const acc_t* __restrict__ Dgh = reinterpret_cast<const acc_t*>(v.Dgh);
   const int t = threadIdx.x;
   const int NJ = v.NJ, n = v.n;
   const bool gl = r < v.n_z;
@@ -550,38 +601,39 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
   double* Jr = J + (size_t)r * n;
   if (gl) {
     const int sub = v.RZ - 1;
-    const double* Ea = v.Eq;
-    const double* Eb = v.Eq + (size_t)v.RZ * NJ;
+    const acc_t* Ea = Eq;
+    const acc_t* Eb = Eq + (size_t)v.RZ * NJ;
     for (int c = t; c < n; c += 256) {
       double val;
       if (c < v.n_z) {
-        val = -d * Tx[c] - Ea[(size_t)i * NJ + c] + Ea[(size_t)sub * NJ + c];
+        val = -d * Tx[c] - (double)Ea[(size_t)i * NJ + c] + (double)Ea[(size_t)sub * NJ + c];
       } else {
         const int j = c - v.n_z;
-        val = -Eb[(size_t)i * NJ + j] + Eb[(size_t)sub * NJ + j];
+        val = -(double)Eb[(size_t)i * NJ + j] + (double)Eb[(size_t)sub * NJ + j];
       }
       Jr[c] = val;
     }
   } else {
     const int sub = v.RG - 1;
-    const double* Eb = v.Eq + (size_t)2 * v.RZ * NJ;
+    const acc_t* Eb = Eq + (size_t)2 * v.RZ * NJ;
     for (int c = t; c < n; c += 256) {
       double val;
       if (c < v.n_z) {
-        val = -v.Dgh[(size_t)i * NJ + c] + v.Dgh[(size_t)sub * NJ + c];
+        val = -(double)Dgh[(size_t)i * NJ + c] + (double)Dgh[(size_t)sub * NJ + c];
       } else {
         const int j = c - v.n_z;
-        val = -d * Tx[j] - Eb[(size_t)i * NJ + j] + Eb[(size_t)sub * NJ + j];
+        val = -d * Tx[j] - (double)Eb[(size_t)i * NJ + j] + (double)Eb[(size_t)sub * NJ + j];
       }
       Jr[c] = val;
     }
   }
-  if (t == 0 && F) row_residual(v, ph, r, F, S);
+  if (F && t < 64) row_residual_wave(v, ph, r, F, S, t);
 }
 
+template <bool MIX>
 __global__ __launch_bounds__(256) void assemble_kernel(Views v, Phys ph, double* __restrict__ J,
                                                        double* F, double* S) {
-  assemble_body(v, ph, blockIdx.x, J, F, S);
+  assemble_body<MIX>(v, ph, blockIdx.x, J, F, S);
 }
 
 // --------------------------------------------------------------------------
@@ -1148,11 +1200,11 @@ __global__ __launch_bounds__(256) void batch_dressing_kernel(const SolveDesc* __
                                                              const int* __restrict__ mask,
                                                              const double* __restrict__ cpk, int which,
                                                              int* counter) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;  // work queue of the next point launch
-  const int b = blockIdx.x;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0;  // queue of the next point launch
+  const int b = blockIdx.y;
   if (!mask[b]) return;
   const SolveDesc& sd = d[b];
-  dressing_body(sd.v, sd.ph, which ? sd.v.ct : cpk + sd.coff);
+  dressing_body(sd.v, sd.ph, which ? sd.v.ct : cpk + sd.coff, blockIdx.x * 256, gridDim.x * 256, blockIdx.x == 0);
 }
 
 // Queue of (problem, kind, row, tile) items, largest first.  The kernel is
@@ -1206,7 +1258,7 @@ __global__ __launch_bounds__(256) void batch_contract_kernel(const SolveDesc* __
   const Views& v = d[b].v;
   const int bx = blockIdx.x, by = blockIdx.y;
   if (bx >= v.Rbp / 16 + (v.RG + 15) / 16 || by >= v.NJ / 16) return;
-  contract_body(v, bx, by);
+  contract_body<false>(v, bx, by);
 }
 
 __global__ __launch_bounds__(256) void batch_assemble_kernel(const SolveDesc* __restrict__ d,
@@ -1215,7 +1267,7 @@ __global__ __launch_bounds__(256) void batch_assemble_kernel(const SolveDesc* __
   if (!mask[b]) return;
   const SolveDesc& sd = d[b];
   if ((int)blockIdx.x >= sd.v.n) return;
-  assemble_body(sd.v, sd.ph, blockIdx.x, sd.v.J, sd.v.F, sd.v.S);
+  assemble_body<false>(sd.v, sd.ph, blockIdx.x, sd.v.J, sd.v.F, sd.v.S);
 }
 
 __global__ __launch_bounds__(256) void batch_residual_rows_kernel(const SolveDesc* __restrict__ d,
@@ -1223,8 +1275,9 @@ __global__ __launch_bounds__(256) void batch_residual_rows_kernel(const SolveDes
   const int b = blockIdx.y;
   if (!mask[b]) return;
   const SolveDesc& sd = d[b];
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r < sd.v.n) row_residual(sd.v, sd.ph, r, which ? sd.v.Ft : sd.v.F, which ? sd.v.St : sd.v.S);
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r < sd.v.n)
+    row_residual_wave(sd.v, sd.ph, r, which ? sd.v.Ft : sd.v.F, which ? sd.v.St : sd.v.S, threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void batch_norms_kernel(const SolveDesc* __restrict__ d,
@@ -1288,46 +1341,51 @@ __global__ __launch_bounds__(256) void batch_pack_kernel(const SolveDesc* __rest
 // launchers
 
 hipError_t launch_dressing(const Views& v, const Phys& ph, const double* c, hipStream_t st) {
-  hipLaunchKernelGGL(dressing_kernel, dim3(1), dim3(256), 0, st, v, ph, c);
+  hipLaunchKernelGGL(dressing_kernel, dim3((v.Qp + v.n + 255) / 256), dim3(256), 0, st, v, ph, c);
   return hipGetLastError();
 }
 
-template <int NJ, int MODE>
+template <int NJ, int MODE, bool MIX>
 static hipError_t points_nj(const Views& v, const Phys& ph, hipStream_t st, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL((point_kernel<GLUON, NJ, MODE>), dim3(v.RZ * v.nqt * v.KS), dim3(256), 0, st, v, ph);
+  hipLaunchKernelGGL((point_kernel<GLUON, NJ, MODE, MIX>), dim3(v.RZ * v.nqt * v.KS), dim3(256), 0, st, v, ph);
   if (ev) (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((point_kernel<GHOST, NJ, MODE>), dim3(v.RG * v.nqt * v.KS), dim3(256), 0, st, v, ph);
+  hipLaunchKernelGGL((point_kernel<GHOST, NJ, MODE, MIX>), dim3(v.RG * v.nqt * v.KS), dim3(256), 0, st, v, ph);
   if (ev) (void)hipEventRecord(ev[2], st);
   return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool MIX>
 static hipError_t points_dispatch(const Views& v, const Phys& ph, hipStream_t st, hipEvent_t* ev) {
   switch (v.NJ) {
-    case 16: return points_nj<16, MODE>(v, ph, st, ev);
-    case 32: return points_nj<32, MODE>(v, ph, st, ev);
-    case 48: return points_nj<48, MODE>(v, ph, st, ev);
-    case 64: return points_nj<64, MODE>(v, ph, st, ev);
-    case 96: return points_nj<96, MODE>(v, ph, st, ev);
-    case 128: return points_nj<128, MODE>(v, ph, st, ev);
+    case 16: return points_nj<16, MODE, MIX>(v, ph, st, ev);
+    case 32: return points_nj<32, MODE, MIX>(v, ph, st, ev);
+    case 48: return points_nj<48, MODE, MIX>(v, ph, st, ev);
+    case 64: return points_nj<64, MODE, MIX>(v, ph, st, ev);
+    case 96: return points_nj<96, MODE, MIX>(v, ph, st, ev);
+    case 128: return points_nj<128, MODE, MIX>(v, ph, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_points(const Views& v, const Phys& ph, int mode, hipStream_t st, hipEvent_t* ev) {
+hipError_t launch_points(const Views& v, const Phys& ph, int mode, bool mix, hipStream_t st, hipEvent_t* ev) {
   switch (mode) {
-    case MODE_RES: return points_dispatch<MODE_RES>(v, ph, st, ev);
-    case MODE_JAC: return points_dispatch<MODE_JAC>(v, ph, st, ev);
-    case MODE_VJP: return points_dispatch<MODE_VJP>(v, ph, st, ev);
-    case MODE_VTH: return points_dispatch<MODE_VTH>(v, ph, st, ev);
+    case MODE_RES: return points_dispatch<MODE_RES, false>(v, ph, st, ev);
+    case MODE_JAC:
+      return mix ? points_dispatch<MODE_JAC, true>(v, ph, st, ev) : points_dispatch<MODE_JAC, false>(v, ph, st, ev);
+    case MODE_VJP: return points_dispatch<MODE_VJP, false>(v, ph, st, ev);
+    case MODE_VTH: return points_dispatch<MODE_VTH, false>(v, ph, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_contract(const Views& v, hipStream_t st) {
+hipError_t launch_contract(const Views& v, bool mix, hipStream_t st) {
   const int gh_blocks = (v.RG + 15) / 16;
-  hipLaunchKernelGGL(contract_kernel, dim3(v.Rbp / 16 + gh_blocks, v.NJ / 16), dim3(256), 0, st, v);
+  const dim3 grid(v.Rbp / 16 + gh_blocks, v.NJ / 16);
+  if (mix)
+    hipLaunchKernelGGL(contract_kernel<true>, grid, dim3(256), 0, st, v);
+  else
+    hipLaunchKernelGGL(contract_kernel<false>, grid, dim3(256), 0, st, v);
   return hipGetLastError();
 }
 
@@ -1341,13 +1399,17 @@ hipError_t launch_vjp_reduce(const Views& v, const double* u, double* uJ, double
   return hipGetLastError();
 }
 
-hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S, hipStream_t st) {
-  hipLaunchKernelGGL(assemble_kernel, dim3(v.n), dim3(256), 0, st, v, ph, J, F, S);
+hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S, bool mix,
+                           hipStream_t st) {
+  if (mix)
+    hipLaunchKernelGGL(assemble_kernel<true>, dim3(v.n), dim3(256), 0, st, v, ph, J, F, S);
+  else
+    hipLaunchKernelGGL(assemble_kernel<false>, dim3(v.n), dim3(256), 0, st, v, ph, J, F, S);
   return hipGetLastError();
 }
 
 hipError_t launch_residual_rows(const Views& v, const Phys& ph, double* F, double* S, hipStream_t st) {
-  hipLaunchKernelGGL(residual_rows_kernel, dim3((v.n + 255) / 256), dim3(256), 0, st, v, ph, F, S);
+  hipLaunchKernelGGL(residual_rows_kernel, dim3((v.n + 3) / 4), dim3(256), 0, st, v, ph, F, S);
   return hipGetLastError();
 }
 
@@ -1410,8 +1472,8 @@ hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, dou
 
 hipError_t launch_batch_dressing(const BatchArgs& a, const double* cpk, int which, int* counter,
                                  hipStream_t st) {
-  hipLaunchKernelGGL(batch_dressing_kernel, dim3(a.count), dim3(256), 0, st, a.desc, a.mask, cpk, which,
-                     counter);
+  hipLaunchKernelGGL(batch_dressing_kernel, dim3(a.max_dress_blocks, a.count), dim3(256), 0, st, a.desc, a.mask, cpk,
+                     which, counter);
   return hipGetLastError();
 }
 
@@ -1481,7 +1543,7 @@ hipError_t launch_batch_assemble(const BatchArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_batch_residual_rows(const BatchArgs& a, int which, hipStream_t st) {
-  hipLaunchKernelGGL(batch_residual_rows_kernel, dim3((a.max_n + 255) / 256, a.count), dim3(256), 0, st, a.desc,
+  hipLaunchKernelGGL(batch_residual_rows_kernel, dim3((a.max_n + 3) / 4, a.count), dim3(256), 0, st, a.desc,
                      a.mask, which);
   return hipGetLastError();
 }
