@@ -158,6 +158,21 @@ dse_status dse_jacobian(dse_ctx* ctx, const double* d_c, double* d_J, double* d_
 dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* opts,
                             dse_newton_report* h_report);
 
+/* One Newton iteration (Sec. 3) in one call: J and F at d_c (kept in the
+ * workspace), the LU solve J Delta = F, d_c_new = d_c - rho Delta, and the
+ * residual at d_c_new into d_F_new (and its scale into d_S_new, nullable).
+ * Enqueued on the context's stream; returns without synchronising unless
+ * check != 0, which synchronises and reports a zero pivot (DSE_E_SINGULAR;
+ * d_c_new is then undefined).  d_c and d_c_new must differ.  With graphs on
+ * (dse_set_graphs, the default) the launch sequence is recorded into a HIP
+ * graph on the first call for a given set of pointers and rho and replayed
+ * afterwards; the arrays must stay allocated while the context uses them.
+ * Stage timings (dse_set_timing) are recorded only with graphs off. */
+dse_status dse_newton_step(dse_ctx* ctx, const double* d_c, double rho, double* d_c_new, double* d_F_new,
+                           double* d_S_new, int32_t check);
+/* Switches the recorded-graph replay of dse_newton_step on (default) or off. */
+dse_status dse_set_graphs(dse_ctx* ctx, int32_t on);
+
 /* Solves J x = b (trans = 0) or J^T x = b (trans != 0) for a row-major
  * n x n d_J with the device LU (partial pivoting).  d_J is not modified; the
  * factors go to the workspace.  d_x may equal d_b. */

@@ -286,6 +286,7 @@ dse_status dse_batch_init(const dse_params* p, int32_t count, void* d_workspace,
       return st;
     }
   }
+  dse::lu_setup();
   B->h_mask.assign(count, 1);
   B->h_rho.assign(count, 1.0);
   // default launch (before any tuning): no angular split, one workgroup per

@@ -31,6 +31,15 @@ struct dse_ctx {
   int ring_count;
   double acc_ms[5];
   int acc_n;
+  // recorded Newton step (dse_newton_step): the launch sequence for one set
+  // of pointers and one relaxation, replayed as a HIP graph
+  bool graphs = true;
+  hipStream_t cap_st = nullptr;  // private stream the graph is recorded on (the
+                                 // caller's stream may be the null stream, which
+                                 // cannot be captured); replays go to st
+  hipGraphExec_t step_exec = nullptr;
+  const void* step_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  double step_rho = 0.0;
   char err[512];
 };
 
@@ -522,6 +531,7 @@ dse_status dse_init(const dse_params* p, void* d_workspace, size_t ws_bytes, voi
         return DSE_E_DEVICE;
       }
     }
+  dse::lu_setup();
   s = build_tables(ctx);
   if (s != DSE_OK) {
     set_err(g_init_err, "%s", ctx->err);
@@ -538,6 +548,8 @@ dse_status dse_destroy(dse_ctx* ctx) {
   if (!ctx) return DSE_OK;
   for (auto& row : ctx->ev)
     for (auto& e : row) (void)hipEventDestroy(e);
+  if (ctx->step_exec) (void)hipGraphExecDestroy(ctx->step_exec);
+  if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
   delete ctx;
   return DSE_OK;
 }
@@ -638,6 +650,84 @@ dse_status dse_set_physics(dse_ctx* ctx, double alpha_mu, double g0_inv, double 
   if (s != DSE_OK) return s;
   ctx->p = p;
   ctx->ph = make_phys(p);
+  return DSE_OK;
+}
+
+namespace {
+
+// The kernels of one Newton step (J, F at c; LU; c_new = c - rho Delta;
+// F, S at c_new), enqueued on the context's stream.
+dse_status enqueue_step(dse_ctx* ctx, const double* c, double rho, double* c_new, double* F_new, double* S_new,
+                        bool capturing) {
+  const dse::Views& v = ctx->v;
+  const bool timing = ctx->timing;
+  if (capturing) ctx->timing = false;  // no stage events inside a recorded graph
+  dse_status s = eval_jacobian(ctx, c, v.J, v.F, v.S);
+  ctx->timing = timing;
+  if (s != DSE_OK) return s;
+  HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, ctx->st));
+  HIP_TRY(ctx, dse::launch_axpy(v.n, c, rho, v.dlt, c_new, ctx->st));
+  return eval_residual(ctx, c_new, F_new, S_new ? S_new : v.St);
+}
+
+}  // namespace
+
+dse_status dse_set_graphs(dse_ctx* ctx, int32_t on) {
+  if (!ctx) return DSE_E_INVALID;
+  ctx->graphs = on != 0;
+  return DSE_OK;
+}
+
+dse_status dse_newton_step(dse_ctx* ctx, const double* d_c, double rho, double* d_c_new, double* d_F_new,
+                           double* d_S_new, int32_t check) {
+  if (!ctx) return DSE_E_INVALID;
+  if (!d_c || !d_c_new || !d_F_new || d_c == d_c_new || !isfinite(rho)) {
+    set_err(ctx->err, "d_c, d_c_new (distinct) and d_F_new are required, rho finite");
+    return DSE_E_INVALID;
+  }
+  DeviceGuard dg(ctx->device);
+  if (!ctx->graphs) {
+    dse_status s = enqueue_step(ctx, d_c, rho, d_c_new, d_F_new, d_S_new, false);
+    if (s != DSE_OK) return s;
+  } else {
+    const void* key[4] = {d_c, d_c_new, d_F_new, d_S_new};
+    const bool hit = ctx->step_exec && ctx->step_rho == rho && memcmp(key, ctx->step_key, sizeof key) == 0;
+    if (!hit) {
+      if (ctx->step_exec) {
+        (void)hipGraphExecDestroy(ctx->step_exec);
+        ctx->step_exec = nullptr;
+      }
+      if (!ctx->cap_st) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking));
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal));
+      const hipStream_t user_st = ctx->st;
+      ctx->st = ctx->cap_st;
+      dse_status s = enqueue_step(ctx, d_c, rho, d_c_new, d_F_new, d_S_new, true);
+      ctx->st = user_st;
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(ctx->cap_st, &g);
+      if (s != DSE_OK || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (s == DSE_OK) set_err(ctx->err, "stream capture failed: %s", hipGetErrorString(ec));
+        return s != DSE_OK ? s : DSE_E_DEVICE;
+      }
+      const hipError_t ei = hipGraphInstantiate(&ctx->step_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        ctx->step_exec = nullptr;
+        set_err(ctx->err, "graph instantiation failed: %s", hipGetErrorString(ei));
+        return DSE_E_DEVICE;
+      }
+      memcpy(ctx->step_key, key, sizeof key);
+      ctx->step_rho = rho;
+    }
+    HIP_TRY(ctx, hipGraphLaunch(ctx->step_exec, ctx->st));
+  }
+  if (check) {
+    int32_t flag = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
+    if (flag == DSE_E_SINGULAR) { set_err(ctx->err, "zero pivot"); return DSE_E_SINGULAR; }
+  }
   return DSE_OK;
 }
 

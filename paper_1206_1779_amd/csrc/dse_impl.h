@@ -124,6 +124,7 @@ hipError_t launch_axpy(int n, const double* c, double rho, const double* d, doub
                        hipStream_t st);
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x,
                            int trans, hipStream_t st);
+void lu_setup();  // LDS attributes of the factorisation kernels (call before any capture)
 
 // Batched family (one launch per stage for all problems whose mask entry is
 // set).  `which` selects the evaluation point and outputs: 0 = the packed

@@ -1430,6 +1430,26 @@ static void set_lu_lds(int bytes) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+template <bool IN_LDS, int MR>
+static void set_batch_lu_lds(int bytes);
+
+// LDS limits of the factorisation kernels (once per process, before any
+// launch: not inside a stream capture).
+static int g_max_lds = -1;
+void lu_setup() {
+  if (g_max_lds >= 0) return;
+  int dev = 0, val = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    val = 64 * 1024;
+  const int dyn = val - kLUStaticBytes;
+  set_lu_lds<true, 2>(dyn);
+  set_lu_lds<true, 4>(dyn);
+  set_batch_lu_lds<true, 2>(dyn);
+  set_batch_lu_lds<true, 4>(dyn);
+  g_max_lds = val;
+}
+
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x, int trans,
                            hipStream_t st) {
   const int n = v.n;
@@ -1437,17 +1457,8 @@ hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, dou
   // factors of [A | b], padded, in dynamic LDS when they fit
   const size_t lds_bytes = (size_t)np * (np + 1) * sizeof(double);
   const size_t static_bytes = kLUStaticBytes;
-  static int max_lds = -1;
-  if (max_lds < 0) {
-    int dev = 0, val = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-      val = 64 * 1024;
-    max_lds = val;
-    const int dyn = max_lds - (int)static_bytes;
-    set_lu_lds<true, 2>(dyn);
-    set_lu_lds<true, 4>(dyn);
-  }
+  lu_setup();
+  const int max_lds = g_max_lds;
   const bool fits = lds_bytes + static_bytes <= (size_t)max_lds;
   if (np <= 128) {
     if (fits)
@@ -1563,17 +1574,8 @@ hipError_t launch_batch_lu(const BatchArgs& a, int* flags, hipStream_t st) {
   const int np = a.max_np;
   const size_t lds_bytes = (size_t)np * (np + 1) * sizeof(double);
   const size_t static_bytes = kLUStaticBytes;
-  static int max_lds = -1;
-  if (max_lds < 0) {
-    int dev = 0, val = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-      val = 64 * 1024;
-    max_lds = val;
-    const int dyn = max_lds - (int)static_bytes;
-    set_batch_lu_lds<true, 2>(dyn);
-    set_batch_lu_lds<true, 4>(dyn);
-  }
+  lu_setup();
+  const int max_lds = g_max_lds;
   const bool fits = lds_bytes + static_bytes <= (size_t)max_lds;
   if (np <= 128) {
     if (fits)

@@ -26,7 +26,7 @@ EXPORTS = [
     "dse_params_default", "dse_workspace_bytes", "dse_init", "dse_destroy", "dse_start_guess",
     "dse_residual", "dse_jacobian", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
     "dse_last_error", "dse_sizes", "dse_set_timing", "dse_read_timings", "dse_vjp",
-    "dse_set_physics",
+    "dse_set_physics", "dse_newton_step", "dse_set_graphs",
     "dse_batch_workspace_bytes", "dse_batch_init", "dse_batch_destroy", "dse_batch_last_error",
     "dse_batch_offsets", "dse_batch_start_guess", "dse_batch_jacobian", "dse_batch_newton_solve",
     "dse_batch_autotune", "dse_batch_set_launch", "dse_batch_get_launch",
@@ -99,6 +99,8 @@ def load():
             "dse_read_timings": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
             "dse_vjp": (C.c_int, [vp, vp, vp, vp, vp]),
             "dse_set_physics": (C.c_int, [vp, C.c_double, C.c_double, C.c_double]),
+            "dse_newton_step": (C.c_int, [vp, vp, C.c_double, vp, vp, vp, C.c_int32]),
+            "dse_set_graphs": (C.c_int, [vp, C.c_int32]),
             "dse_batch_workspace_bytes": (C.c_size_t, [P, C.c_int32]),
             "dse_batch_init": (C.c_int, [P, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "dse_batch_destroy": (C.c_int, [vp]),
@@ -254,6 +256,20 @@ class Solver:
                             relax_hist=list(rep.relax_hist[: rep.iters]),
                             n_jacobians=rep.n_jacobians, n_residuals=rep.n_residuals,
                             t_total_ms=rep.t_total_ms)
+
+    def newton_step(self, c, rho: float = 1.0, out=None, check: bool = False):
+        """One Newton iteration: returns (c_new, F(c_new), S(c_new)).  `out`
+        (optional) is a tuple of three preallocated vectors; reusing the same
+        ones lets the library replay its recorded graph."""
+        c = self._vec(c)
+        cn, F, S = out if out is not None else (self._vec(), self._vec(), self._vec())
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_newton_step(self.h, _ptr(c), float(rho), _ptr(cn), _ptr(F), _ptr(S),
+                                                 1 if check else 0))
+        return cn, F, S
+
+    def set_graphs(self, on: bool = True):
+        self._check(self.lib.dse_set_graphs(self.h, 1 if on else 0))
 
     def vjp(self, c, u, with_c: bool = True):
         """u^T dF/dc (or None) and u^T dF/d(alpha_mu, g0_inv, z_lambda_inv)."""

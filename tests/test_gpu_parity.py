@@ -188,3 +188,40 @@ def test_noconv_reports_last_iterate(ref, dse):
     F = ref.residual(p, _np(res.c))
     S = ref.residual_scale(p, _np(res.c))
     assert abs(np.max(np.abs(F) / S) - res.fnorm) <= 1e-9 * res.fnorm
+
+
+def test_newton_step_matches_composed_calls_and_graph_replays(ref, dse):
+    """dse_newton_step (J, LU, update, trial residual in one call) against the
+    same step composed from dse_jacobian, dse_lu_solve and dse_residual, eager
+    and replayed from its recorded graph several times (with other work and
+    synchronisations between replays), bit for bit; and the trial residual
+    against the oracle."""
+    import torch
+    cfg = workloads.config("cfg2")
+    p, s = _both(ref, dse, cfg)
+    c0 = s.start_guess()
+    J, F = s.jacobian(c0)
+    d = s.lu_solve(J, F)
+    c_ref = c0 - d
+    F_ref, S_ref = s.residual(c_ref, with_scale=True)
+    s.set_graphs(False)
+    cn, Fn, Sn = s.newton_step(c0, check=True)
+    assert torch.equal(cn, c_ref) and torch.equal(Fn, F_ref) and torch.equal(Sn, S_ref)
+    s.set_graphs(True)
+    out = (torch.empty_like(c0), torch.empty_like(c0), torch.empty_like(c0))
+    for k in range(4):
+        for t in out:
+            t.fill_(float("nan"))
+        cn, Fn, Sn = s.newton_step(c0, out=out, check=(k == 0))
+        torch.cuda.synchronize()
+        assert torch.equal(cn, c_ref) and torch.equal(Fn, F_ref) and torch.equal(Sn, S_ref), k
+        s.residual(c_ref)          # other work on the stream between replays
+        _ = (c0 * 2.0).sum().item()
+    # a second set of outputs records a new graph; relaxation 0.5 as well
+    out2 = (torch.empty_like(c0), torch.empty_like(c0), torch.empty_like(c0))
+    cn2, Fn2, _ = s.newton_step(c0, rho=0.5, out=out2)
+    c_half = c0 - 0.5 * d
+    assert torch.allclose(cn2, c_half, rtol=0, atol=1e-15 * float(c0.abs().max()))
+    Fr = ref.residual(p, _np(cn2))
+    Sr = ref.residual_scale(p, _np(cn2))
+    assert np.all(np.abs(_np(Fn2) - Fr) <= 1e-13 * Sr)
