@@ -190,9 +190,9 @@ __device__ __forceinline__ void slice_reduce(T* vals, int lane, int& base, bool&
 enum { MODE_RES = 0, MODE_JAC = 1, MODE_VJP = 2, MODE_VTH = 3 };
 
 // LDS of one point-kernel block (doubles): red[3][4] at 0, bs[2][4][64] at 16,
-// ds[4][NT*NJ] at 528.
+// ds[4][NT*NJ] at 528, the coefficients a | b at 528 + 8 NJ.
 template <int NJ>
-__host__ __device__ constexpr int point_smem() { return 528 + 8 * NJ; }
+__host__ __device__ constexpr int point_smem() { return 528 + 10 * NJ; }
 
 template <int KIND, int NJ, int MODE, bool MIX = false>
 __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int row, int tile,
@@ -241,8 +241,12 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     pref = -ph.C * W * y;
   }
 
-  const double* __restrict__ ca = v.coef;
-  const double* __restrict__ cb = v.coef + NJ;
+  // coefficients in LDS: every angle re-reads them with broadcast loads (held
+  // in scalar registers they do not fit beside the uniform constants and end
+  // up parked in vector-register lanes, read back one half at a time)
+  double* __restrict__ cl = smem + 528 + 8 * NJ;
+  for (int j = t; j < 2 * NJ; j += 256) cl[j] = v.coef[j];
+  __syncthreads();
   const double* __restrict__ ang = v.ang;
   const int Kp = v.Kp;
   const double rw = WEIGHTED ? v.rw[growrow] : 1.0;
@@ -257,6 +261,8 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   const int member = lane & (G - 1);
 
   for (int k = ks * 4 + wave; k < Kp; k += 4 * KS) {
+    const double* __restrict__ cal = cl;
+    const double* __restrict__ cbl = cl + NJ;
     const double ck = ang[k];
     const double s2h = ang[Kp + k];
     const double wk = KIND == GLUON ? ang[2 * Kp + k] : ang[3 * Kp + k];
@@ -268,20 +274,39 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     s = fmin(fmax(s, -1.0), 1.0);
     const double s2 = s + s;
 
-    // ---- pass 1: recurrence and series (coefficients are wave-uniform)
-    double sa = ca[0], sb = KIND == GLUON ? cb[0] : 0.0;
-    double Tp = 1.0, Tc = s;
+    // ---- pass 1: recurrence and series.  The coefficients are wave-uniform
+    // and read from LDS a chunk at a time; the chunk loop stays a loop, so they
+    // are neither held in registers across it nor gathered at its top.
+    double sa = 0.0, sb = 0.0;
+    double Tp = s, Tc = 1.0;  // (T_{-1}, T_0)
     double stp[G > 1 ? G : 1], stc[G > 1 ? G : 1];
-    stp[0] = s; stc[0] = 1.0;  // (T_{-1}, T_0)
+    // chunk width: a divisor of the pass-2 slice width JT, so that every start
+    // pair falls on a chunk boundary
+    constexpr int CH = (G == 1 || JT % 8 == 0) ? 8 : 4;
+    static_assert(NJ % CH == 0 && (G == 1 || JT % CH == 0), "chunks must tile the slices");
+#pragma clang loop unroll(disable)
+    for (int j0 = 0; j0 < NJ; j0 += CH) {
+      if (G > 1 && (j0 % JT) == 0) {  // start pairs (T_{m JT - 1}, T_{m JT}) of pass 2
 #pragma unroll
-    for (int j = 1; j < NJ; ++j) {
-      if (G > 1 && (j % JT) == 0) { stp[j / JT] = Tp; stc[j / JT] = Tc; }
-      sa = fma(ca[j], Tc, sa);
-      if (KIND == GLUON) sb = fma(cb[j], Tc, sb);
-      const double Tn = fma(s2, Tc, -Tp);
-      Tp = Tc;
-      Tc = Tn;
+        for (int m = 0; m < G; ++m)
+          if (m * JT == j0) { stp[m] = Tp; stc[m] = Tc; }
+      }
+      double c8a[CH], c8b[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        c8a[u] = cal[j0 + u];
+        c8b[u] = KIND == GLUON ? cbl[j0 + u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        sa = fma(c8a[u], Tc, sa);
+        if (KIND == GLUON) sb = fma(c8b[u], Tc, sb);
+        const double Tn = fma(s2, Tc, -Tp);
+        Tp = Tc;
+        Tc = Tn;
+      }
     }
+    if (G == 1) { stp[0] = s; stc[0] = 1.0; }
     double XZ = 0.0, XG = 0.0, dXa = 0.0;  // dXa: d ln(1 + omega l) / d alpha (UV)
     if (lz < ph.ln_eps2) {
       XZ = 2.0 * ph.kappa * (lz - ph.ln_eps2);
@@ -695,19 +720,19 @@ __global__ void axpy_kernel(int n, const double* c, double rho, const double* d,
 // when it does not fit).  The matrix is padded to np = 16 ceil(n/16) with an
 // identity block (padded rows have zeros in the real columns, so they are
 // never chosen as a pivot and the real factors are unchanged) and the
-// right-hand side is column np.  Blocked right-looking elimination, panel
-// width 16:
+// right-hand side is column np.  Rows never move: a map from row position to
+// physical row (rmap) carries the interchanges, and every access to a row
+// position goes through it.  Blocked right-looking elimination, panel width 16:
 //   panel    wave 0 holds the rows of the panel (MR per lane) in registers
 //            and factors it column by column: pivot = largest |a| (wave
 //            maximum by DPP; among equal maxima the first register row), the
 //            pivot row's entries broadcast through LDS, multipliers
-//            a * (1 / pivot), rank-1 update.  Interchanges are only recorded
-//            (a register row carries its logical position); the panel's
-//            columns go back to memory by physical row;
-//   swaps    the panel's interchanges, applied to every column at once;
+//            a * (1 / pivot), rank-1 update.  Interchanges only change the
+//            logical positions of the register rows; at the end the panel's
+//            columns go back to their physical rows and rmap is updated;
 //   U12      U12 = L11^{-1} A12, one column per thread;
-//   update   A22 -= L21 U12 on v_mfma_f64_16x16x4f64 (16 x 16 tiles over
-//            the four waves); the right-hand-side column on the vector ALUs.
+//   update   A22 -= L21 U12 on v_mfma_f64_16x16x4f64 (16 x 16 tiles, two at
+//            a time per wave); the right-hand-side column on the vector ALUs.
 // The right-hand-side column ends as L^{-1} P b; wave 0 back-substitutes by
 // blocks of 16 rows with the reciprocal pivots kept from the panels.  The
 // transposed solve (A^T x = b) runs U^T, L^T and P^T with wave 0.
@@ -756,11 +781,10 @@ __device__ __forceinline__ void wave_memory_sync() {
 // Shared state of one factorisation.
 struct LUShared {
   int spiv[256];     // spiv[k]: position interchanged with k at step k
+  int rmap[256];     // row position -> physical row
   double dinv[256];  // 1 / U[k][k]
   double wsv[256];   // staging of the transposed solve
   double ub[LU_NB];  // pivot row broadcast
-  int mv_src[2 * LU_NB], mv_dst[2 * LU_NB];  // rows moved by a panel's interchanges
-  int nmv;
   int sing;
 };
 
@@ -789,20 +813,26 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
     if (lp < 0 && mk) { lp = (int)__builtin_ctzll(mk); mp = m; }
   }
   int lsel = lpos[0];
+  double psel = P[0][O];
 #pragma unroll
-  for (int m = 1; m < MR; ++m) if (mp == m) lsel = lpos[m];
+  for (int m = 1; m < MR; ++m)
+    if (mp == m) { lsel = lpos[m]; psel = P[m][O]; }
   const int p = __builtin_amdgcn_readlane(lsel, lp);
-  wave_memory_sync();  // the previous column's reads of ub are done
+  const double inv = 1.0 / readlane_d(psel, lp);  // overlaps the broadcast below
+  // (the previous column's reads of ub precede these writes in every lane)
   if (lane == lp) {
 #pragma unroll
-    for (int cc = O; cc < CE; ++cc) {
+    for (int cc = O + 1; cc < CE; ++cc) {
       double sel = P[0][cc];
 #pragma unroll
       for (int m = 1; m < MR; ++m) if (mp == m) sel = P[m][cc];
       sh.ub[cc] = sel;
     }
   }
-  if (lane == 0) sh.spiv[kc] = p;
+  if (lane == 0) {
+    sh.spiv[kc] = p;
+    sh.dinv[kc] = inv;
+  }
   if (p != kc) {
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
@@ -813,25 +843,22 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
   wave_memory_sync();
   double rp[CE];
 #pragma unroll
-  for (int cc = O; cc < CE; ++cc) rp[cc] = sh.ub[cc];
-  const double inv = 1.0 / rp[O];
-  if (lane == 0) sh.dinv[kc] = inv;
+  for (int cc = O + 1; cc < CE; ++cc) rp[cc] = sh.ub[cc];
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
-    if (lpos[m] > kc) {
-      const double l = P[m][O] * inv;
-      P[m][O] = l;
+    const bool below = lpos[m] > kc;
+    const double l = below ? P[m][O] * inv : 0.0;
+    if (below) P[m][O] = l;
 #pragma unroll
-      for (int cc = O + 1; cc < CE; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
-    }
+    for (int cc = O + 1; cc < CE; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
   }
 }
 
 // Columns G .. LU_NB - 1 of the panel, four at a time; each group's four
-// finished columns go back to memory (by physical row) before the shift.
+// finished columns go back to the physical rows before the shift.
 template <int MR, int G>
-__device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR], double* M, int ld, int lane,
-                                         int k0, LUShared& sh, int& sg) {
+__device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR], const int (&phys)[MR], double* M,
+                                         int ld, int lane, int k0, LUShared& sh, int& sg) {
   lu_col<MR, 0, G>(P, lpos, sh, lane, k0 + G + 0, sg);
   if (sg) return;
   lu_col<MR, 1, G>(P, lpos, sh, lane, k0 + G + 1, sg);
@@ -843,7 +870,7 @@ __device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR]
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     if (lpos[m] >= 0) {
-      double* Mr = M + (size_t)(k0 + lane + 64 * m) * ld + k0 + G;
+      double* Mr = M + (size_t)phys[m] * ld + k0 + G;
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) Mr[cc] = P[m][cc];
     }
@@ -854,7 +881,7 @@ __device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR]
 #pragma unroll
       for (int cc = 0; cc < LU_NB - G - 4; ++cc) P[m][cc] = P[m][cc + 4];
     }
-    lu_panel<MR, G + 4>(P, lpos, M, ld, lane, k0, sh, sg);
+    lu_panel<MR, G + 4>(P, lpos, phys, M, ld, lane, k0, sh, sg);
   }
 }
 
@@ -869,13 +896,14 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   const int ncol = np + 1;
   double* M = IN_LDS ? lds : Aglob;
   __shared__ LUShared sh;
-  // load [A | b] padded with an identity block, sixteen loads in flight
+  const int* __restrict__ rmap = sh.rmap;
+  // load [A | b] padded with an identity block, 64 loads in flight per thread
   {
     const int tot = np * np;
-    for (int e0 = t; e0 < tot; e0 += 256 * 16) {
-      double v_[16];
+    for (int e0 = t; e0 < tot; e0 += 256 * 64) {
+      double v_[64];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < 64; ++u) {
         const int e = e0 + 256 * u;
         const int r = e / np, c = e - r * np;
         double val = (r == c) ? 1.0 : 0.0;
@@ -883,7 +911,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
         v_[u] = val;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < 64; ++u) {
         const int e = e0 + 256 * u;
         if (e < tot) {
           const int r = e / np, c = e - r * np;
@@ -891,7 +919,10 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
         }
       }
     }
-    for (int r = t; r < np; r += 256) M[(size_t)r * ld + np] = (r < n && !trans) ? b[r] : 0.0;
+    for (int r = t; r < np; r += 256) {
+      M[(size_t)r * ld + np] = (r < n && !trans) ? b[r] : 0.0;
+      sh.rmap[r] = r;
+    }
   }
   if (t == 0) sh.sing = 0;
   __syncthreads();
@@ -899,100 +930,98 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   for (int k0 = 0; k0 < np; k0 += LU_NB) {
     if (wave == 0) {
       double P[MR][LU_NB];
-      int lpos[MR];
+      int lpos[MR], phys[MR];
 #pragma unroll
       for (int m = 0; m < MR; ++m) {
-        const int r = k0 + lane + 64 * m;
-        lpos[m] = r < np ? r : -1;  // -1: no row (never a candidate, never updated)
+        const int pos = k0 + lane + 64 * m;
+        lpos[m] = pos < np ? pos : -1;  // -1: no row (never a candidate, never updated)
+        phys[m] = pos < np ? rmap[pos] : 0;
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) P[m][c] = r < np ? M[(size_t)r * ld + k0 + c] : 0.0;
+        for (int c = 0; c < LU_NB; ++c) P[m][c] = pos < np ? M[(size_t)phys[m] * ld + k0 + c] : 0.0;
       }
       int sg = 0;
-      lu_panel<MR, 0>(P, lpos, M, ld, lane, k0, sh, sg);
+      lu_panel<MR, 0>(P, lpos, phys, M, ld, lane, k0, sh, sg);
       if (sg) {
         if (lane == 0) sh.sing = 1;
       } else {
-        // rows whose position changed: physical row -> final position
-        int base = 0;
+        wave_memory_sync();  // every lane has read rmap before it changes
 #pragma unroll
-        for (int m = 0; m < MR; ++m) {
-          const int r = k0 + lane + 64 * m;
-          const bool moved = lpos[m] >= 0 && lpos[m] != r;
-          const unsigned long long mk = __ballot(moved);
-          if (moved) {
-            const int idx = base + __builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
-            sh.mv_src[idx] = r;
-            sh.mv_dst[idx] = lpos[m];
-          }
-          base += __builtin_popcountll(mk);
-        }
-        if (lane == 0) sh.nmv = base;
+        for (int m = 0; m < MR; ++m)
+          if (lpos[m] >= 0) sh.rmap[lpos[m]] = phys[m];
       }
     }
     __syncthreads();
     if (sh.sing) break;
-    // the panel's interchanges applied to every column (columns left of the
-    // panel hold L and only matter to the transposed solve)
+    const int j0 = k0 + LU_NB;
+    // U12 = L11^{-1} A12: one column per thread, in registers, column-oriented
+    // (step cc subtracts L11[:, cc] u[cc] from the rows below: a dependency
+    // chain of 15 steps); after the last panel only the right-hand side is left
     {
-      const int nmv = sh.nmv;
-      for (int j = (trans ? 0 : k0) + t; j < ncol; j += 256) {
-        double tmp[2 * LU_NB];
+      int pr[LU_NB];
 #pragma unroll
-        for (int q = 0; q < 2 * LU_NB; ++q)
-          if (q < nmv) tmp[q] = M[(size_t)sh.mv_src[q] * ld + j];
+      for (int c = 0; c < LU_NB; ++c) pr[c] = rmap[k0 + c];
+      for (int j = j0 + t; j < ncol; j += 256) {
+        double u[LU_NB];
 #pragma unroll
-        for (int q = 0; q < 2 * LU_NB; ++q)
-          if (q < nmv) M[(size_t)sh.mv_dst[q] * ld + j] = tmp[q];
+        for (int c = 0; c < LU_NB; ++c) u[c] = M[(size_t)pr[c] * ld + j];
+#pragma unroll
+        for (int cc = 0; cc < LU_NB - 1; ++cc) {
+#pragma unroll
+          for (int c = cc + 1; c < LU_NB; ++c) u[c] = fma(-M[(size_t)pr[c] * ld + k0 + cc], u[cc], u[c]);
+        }
+#pragma unroll
+        for (int c = 1; c < LU_NB; ++c) M[(size_t)pr[c] * ld + j] = u[c];
       }
-    }
-    __syncthreads();
-    const int j0 = k0 + LU_NB;  // (after the last panel only the right-hand side is left of U12)
-    // U12 = L11^{-1} A12: one column per thread, in registers
-    for (int j = j0 + t; j < ncol; j += 256) {
-      double u[LU_NB];
-#pragma unroll
-      for (int c = 0; c < LU_NB; ++c) u[c] = M[(size_t)(k0 + c) * ld + j];
-#pragma unroll
-      for (int c = 1; c < LU_NB; ++c) {
-        const double* Lr = M + (size_t)(k0 + c) * ld + k0;
-        double s_ = u[c];
-#pragma unroll
-        for (int cc = 0; cc < c; ++cc) s_ = fma(-Lr[cc], u[cc], s_);
-        u[c] = s_;
-      }
-#pragma unroll
-      for (int c = 1; c < LU_NB; ++c) M[(size_t)(k0 + c) * ld + j] = u[c];
     }
     __syncthreads();
     // A22 -= L21 U12 on the matrix cores: tile (ti, tj) of 16 x 16; operands
     // A[i][k] = -L21 in lane i + 16 k, B[k][j] = U12 in lane j + 16 k, the
-    // tile itself as accumulator (lane l, register r: row l/16 + 4 r, column l % 16)
-    {
+    // tile itself as accumulator (lane l, register r: row l/16 + 4 r,
+    // column l % 16); two tiles of the same tile row per step
+    if (j0 < np) {
       const int nt = (np - j0) / 16;
       const int li = lane & 15, lk = lane >> 4;
-      for (int e = wave; e < nt * nt; e += 4) {
-        const int ti = e / nt, tj = e - ti * nt;
-        const int i0 = j0 + 16 * ti, c0 = j0 + 16 * tj;
-        d4 acc;
+      int brow[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = M[(size_t)(i0 + lk + 4 * r) * ld + c0 + li];
+      for (int s = 0; s < 4; ++s) brow[s] = rmap[k0 + 4 * s + lk];
+      const int npair = (nt + 1) / 2;
+      for (int e = wave; e < nt * npair; e += 4) {
+        const int ti = e / npair, tp = e - ti * npair;
+        const int i0 = j0 + 16 * ti;
+        const int c0 = j0 + 32 * tp, c1 = c0 + 16;
+        const bool two = c1 < np;
+        const int arow = rmap[i0 + li];
+        int crow[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double a = -M[(size_t)(i0 + li) * ld + k0 + 4 * s + lk];
-          const double bb = M[(size_t)(k0 + 4 * s + lk) * ld + c0 + li];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        for (int r = 0; r < 4; ++r) crow[r] = rmap[i0 + lk + 4 * r];
+        d4 acc0, acc1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc0[r] = M[(size_t)crow[r] * ld + c0 + li];
+          acc1[r] = two ? M[(size_t)crow[r] * ld + c1 + li] : 0.0;
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) M[(size_t)(i0 + lk + 4 * r) * ld + c0 + li] = acc[r];
+        for (int s = 0; s < 4; ++s) {
+          const double a = -M[(size_t)arow * ld + k0 + 4 * s + lk];
+          const double b0 = M[(size_t)brow[s] * ld + c0 + li];
+          const double b1 = two ? M[(size_t)brow[s] * ld + c1 + li] : 0.0;
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          M[(size_t)crow[r] * ld + c0 + li] = acc0[r];
+          if (two) M[(size_t)crow[r] * ld + c1 + li] = acc1[r];
+        }
       }
       // right-hand-side column
       for (int i = j0 + t; i < np; i += 256) {
-        const double* Li = M + (size_t)i * ld + k0;
-        double s_ = M[(size_t)i * ld + np];
+        const int pi_ = rmap[i];
+        const double* Li = M + (size_t)pi_ * ld + k0;
+        double s_ = M[(size_t)pi_ * ld + np];
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) s_ = fma(-Li[c], M[(size_t)(k0 + c) * ld + np], s_);
-        M[(size_t)i * ld + np] = s_;
+        for (int c = 0; c < LU_NB; ++c) s_ = fma(-Li[c], M[(size_t)rmap[k0 + c] * ld + np], s_);
+        M[(size_t)pi_ * ld + np] = s_;
       }
     }
     __syncthreads();
@@ -1003,26 +1032,35 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   }
   for (int i = t; i < n; i += 256) piv[i] = sh.spiv[i];
   if (wave != 0) return;
-  // wave 0: w distributed as rows lane + 64 m
+  // wave 0: w distributed as row positions lane + 64 m
   double w[MR];
+  int prow[MR];  // physical row of position lane + 64 m
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const int r = lane + 64 * m;
+    prow[m] = r < np ? rmap[r] : 0;
+  }
   if (!trans) {
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
       const int r = lane + 64 * m;
-      w[m] = r < np ? M[(size_t)r * ld + np] : 0.0;  // = L^{-1} P b
+      w[m] = r < np ? M[(size_t)prow[m] * ld + np] : 0.0;  // = L^{-1} P b
     }
     // U x = y by blocks of 16 rows from the bottom: solve the diagonal block
     // (values broadcast by lane reads), then update the rows above
     for (int i1 = np; i1 > 0; i1 -= LU_NB) {
       const int i0 = i1 - LU_NB;
       const int mi = i0 >> 6;
-      double xb[LU_NB], ub[MR][LU_NB];
+      double xb[LU_NB], ub[MR][LU_NB], dv[LU_NB];
+#pragma unroll
+      for (int cc = 0; cc < LU_NB; ++cc) dv[cc] = sh.dinv[i0 + cc];
 #pragma unroll
       for (int m = 0; m < MR; ++m) {
         const int r = lane + 64 * m;
         const bool in = r >= i0 && r < i1;
+        const double* Ur = M + (size_t)prow[m] * ld + i0;
 #pragma unroll
-        for (int cc = 0; cc < LU_NB; ++cc) ub[m][cc] = in ? M[(size_t)r * ld + i0 + cc] : 0.0;
+        for (int cc = 0; cc < LU_NB; ++cc) ub[m][cc] = in ? Ur[cc] : 0.0;
       }
 #pragma unroll
       for (int cc = LU_NB - 1; cc >= 0; --cc) {
@@ -1030,7 +1068,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
         double sel = w[0];
 #pragma unroll
         for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
-        const double xi = readlane_d(sel, i & 63) * sh.dinv[i];
+        const double xi = readlane_d(sel, i & 63) * dv[cc];
         xb[cc] = xi;
 #pragma unroll
         for (int m = 0; m < MR; ++m) {
@@ -1043,7 +1081,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       for (int m = 0; m < MR; ++m) {
         const int r = lane + 64 * m;
         if (r < i0) {
-          const double* Ur = M + (size_t)r * ld + i0;
+          const double* Ur = M + (size_t)prow[m] * ld + i0;
           double s_ = w[m];
 #pragma unroll
           for (int cc = 0; cc < LU_NB; ++cc) s_ = fma(-Ur[cc], xb[cc], s_);
@@ -1059,6 +1097,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
     }
     for (int i = 0; i < np; ++i) {  // U^T y = b
       const int li = i & 63, mi = i >> 6;
+      const double* Ui = M + (size_t)rmap[i] * ld;
       double sel = w[0];
 #pragma unroll
       for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
@@ -1067,11 +1106,12 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       for (int m = 0; m < MR; ++m) {
         const int r = lane + 64 * m;
         if (r == i) w[m] = yi;
-        else if (r > i && r < np) w[m] = fma(-M[(size_t)i * ld + r], yi, w[m]);
+        else if (r > i && r < np) w[m] = fma(-Ui[r], yi, w[m]);
       }
     }
     for (int i = np - 1; i >= 0; --i) {  // L^T z = y (unit diagonal)
       const int li = i & 63, mi = i >> 6;
+      const double* Li = M + (size_t)rmap[i] * ld;
       double sel = w[0];
 #pragma unroll
       for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
@@ -1079,7 +1119,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
 #pragma unroll
       for (int m = 0; m < MR; ++m) {
         const int r = lane + 64 * m;
-        if (r < i) w[m] = fma(-M[(size_t)i * ld + r], zi, w[m]);
+        if (r < i) w[m] = fma(-Li[r], zi, w[m]);
       }
     }
     // x = P^T z: undo the interchanges in reverse order (staged in LDS)
