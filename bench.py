@@ -219,6 +219,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--solves", type=int, default=5, help="Newton solves timed for s/solve")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint comparisons")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device five times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and has no "
@@ -230,6 +232,15 @@ def main() -> int:
     from paper_1206_1779_amd import dse
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "launches": 5}), flush=True)
+        return 0
     name = "cfg2"
     cfg = workloads.config(name)
     s = dse.Solver(device="cuda:0", **cfg)
@@ -282,7 +293,9 @@ def main() -> int:
             "ghost_kernel_ms": stages[2], "ghost_kernel_tflops": ghost_point_flops(cfg) / (stages[2] * 1e-3) / 1e12}
 
     # s / Newton solve from the start guess to scaled residual < 1e-10
-    times, iters = [], []
+    times, iters = [float("nan")], [0]
+    if args.solves > 0:
+        times, iters = [], []
     for _ in range(args.solves):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
