@@ -50,6 +50,26 @@ def ghost_point_flops(cfg: dict) -> float:
     return pts * (6 * nz + GHOST_SCALAR_FLOPS)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs summarised under profiles/, or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "point_kernel_gluon_n64_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1206_1779_amd", "csrc", "dse_kernels.hip")
+    try:
+        vals = {}
+        for line in open(path):
+            k, _, v = line.strip().partition(": ")
+            vals[k] = v
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if vals.get("kernel_source_sha256") != sha or vals.get("traffic_kernel") != kernel:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(cfg: dict, c, cpu_seconds: float = 20.0, max_steps: int = 50) -> dict:
     """The oracle (plain FP64 C, OpenMP over rows, all host threads) doing the
     same step on the host, repeated until about `cpu_seconds` of CPU time
@@ -287,7 +307,8 @@ def main() -> int:
     achieved = a_gl / t_gl / 1e12
     roof = {"bound": "alu", "kernel": "point_kernel<gluon, 64, jacobian>",
             "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+            "traffic": measured_traffic("void dse::point_kernel<0, 64, 1, false>"),
             "flops_per_launch": a_gl, "avg_launch_ms": t_gl * 1e3, "launches": cnt,
             "timed": "HIP events around each launch over the second pass of the same steps",
             "ghost_kernel_ms": stages[2], "ghost_kernel_tflops": ghost_point_flops(cfg) / (stages[2] * 1e-3) / 1e12}
