@@ -224,6 +224,7 @@ def bench_mixed(dse, workloads, torch) -> dict:
         out["newton_s_" + k] = time.perf_counter() - t0
         out["newton_iters_" + k] = r.iters
         out["newton_status_" + k] = r.status
+        out["newton_fp32_matrices_" + k] = r.n_jacobians_mixed
         roots[k] = r.c
     dc = (roots["mixed"] - roots["fp64"]).abs()
     out["root_max_abs_diff"] = float(dc.max())

@@ -59,6 +59,11 @@ typedef enum {
   DSE_E_NONFINITE = 6  /* residual or Jacobian not finite                      */
 } dse_status;
 
+/* DSE_MIXED: the Newton matrix's derivative sums and its B.T contraction in
+ * FP32 (F, its scale, norms and the LU stay FP64).  dse_newton_solve uses
+ * FP32 matrices while a step at least halves the 2-norm merit and the scaled
+ * residual is above 1e-6, FP64 ones afterwards; the root is that of the FP64
+ * residual either way. */
 typedef enum { DSE_FP64 = 0, DSE_MIXED = 1 } dse_precision;
 
 typedef struct dse_ctx dse_ctx; /* opaque */
@@ -114,6 +119,8 @@ typedef struct {
   int32_t n_jacobians;     /* assemblies of J and F                               */
   int32_t n_residuals;     /* residual-only evaluations (line search)             */
   double t_total_ms;       /* wall time of the call                               */
+  int32_t n_jacobians_mixed; /* of n_jacobians, those with FP32 derivative sums   */
+  int32_t reserved2_;
 } dse_newton_report;
 
 /* Fills *p with the physics defaults above and the small grid

@@ -240,8 +240,8 @@ size_t layout(const dse_params& p, Views* v, char* base, int ks) {
   t.Dp = (double*)take((size_t)(2 * t.RZ + t.RG) * t.nqt * t.KS * t.NJ * d);
   t.Pip = (double*)take((size_t)2 * (t.RZ + t.RG) * t.nqt * t.KS * d);
   t.Absp = (double*)take((size_t)(t.RZ + t.RG) * t.nqt * t.KS * d);
-  t.Eq = (double*)take((size_t)t.Rbp * t.NJ * d);
-  t.Dgh = (double*)take((size_t)t.RG * t.NJ * d);
+  t.Eq = (double*)take((size_t)dse::kCS * t.Rbp * t.NJ * d);
+  t.Dgh = (double*)take((size_t)dse::kCS * t.RG * t.NJ * d);
   t.rw = (double*)take((size_t)(t.RZ + t.RG) * d);
   const size_t np16 = (size_t)(t.n + 15) / 16 * 16;
   t.LU = (double*)take(np16 * (np16 + 1) * d);  // padded [A | b] when it does not fit LDS
@@ -405,7 +405,8 @@ dse_status eval_residual(dse_ctx* ctx, const double* c, double* F, double* S) {
 
 dse_status flush_timings(dse_ctx* ctx);
 
-dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, double* S) {
+// mix < 0: the context's precision; 0: FP64; 1: FP32 derivative sums
+dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, double* S, int mix_override = -1) {
   const dse::Views& v = ctx->v;
   hipEvent_t* ev = nullptr;
   if (ctx->timing) {
@@ -417,7 +418,7 @@ dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, do
   }
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[0], ctx->st));
   HIP_TRY(ctx, dse::launch_dressing(v, ctx->ph, c, ctx->st));
-  const bool mix = ctx->p.precision == DSE_MIXED;
+  const bool mix = mix_override < 0 ? ctx->p.precision == DSE_MIXED : mix_override != 0;
   HIP_TRY(ctx, dse::launch_points(v, ctx->ph, 1, mix, ctx->st, ev ? ev + 1 : nullptr));
   HIP_TRY(ctx, dse::launch_contract(v, mix, ctx->st));
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[4], ctx->st));
@@ -761,6 +762,10 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
   int it = 0, extra = 0;
   dse_status status = s;
   if (s == DSE_OK && !isfinite(f)) status = DSE_E_NONFINITE;
+  // mixed precision: FP32 Newton matrices while they make progress, FP64 ones
+  // once a step reduces the merit by less than half or it is below 1e-6 (the
+  // FP32 matrix then limits the linear convergence rate)
+  bool use_mix = ctx->p.precision == DSE_MIXED;
   while (status == DSE_OK) {
     if (f < o.tol) {
       if (extra >= o.extra_iters) break;
@@ -768,8 +773,9 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
     }
     if (it >= o.max_iter) { status = DSE_E_NOCONV; break; }
     // J and F at c (F is recomputed with J; it is the same evaluation)
-    if ((s = eval_jacobian(ctx, d_c, v.J, v.F, v.S)) != DSE_OK) { status = s; break; }
+    if ((s = eval_jacobian(ctx, d_c, v.J, v.F, v.S, use_mix ? 1 : 0)) != DSE_OK) { status = s; break; }
     ++r.n_jacobians;
+    if (use_mix) ++r.n_jacobians_mixed;
     if (hipGetLastError() != hipSuccess) { status = DSE_E_DEVICE; break; }
     HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, st));
     const bool conv = f < o.tol;
@@ -795,6 +801,7 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
     HIP_TRY(ctx, hipMemcpyAsync(d_c, v.ct, n * 8, hipMemcpyDeviceToDevice, st));
     HIP_TRY(ctx, hipMemcpyAsync(v.F, v.Ft, n * 8, hipMemcpyDeviceToDevice, st));
     HIP_TRY(ctx, hipMemcpyAsync(v.S, v.St, n * 8, hipMemcpyDeviceToDevice, st));
+    if (use_mix && (ft2 > 0.5 * f2 || ft < 1e-6)) use_mix = false;
     f = ft;
     f2 = ft2;
     ++it;

@@ -15,6 +15,8 @@ namespace dse {
 constexpr int kQPad = 64;
 constexpr int kKPad = 8;
 constexpr double kPi = 3.14159265358979323846264338327950288;
+// parts of the radial sum of the B . T contraction (summed by the assembly)
+constexpr int kCS = 4;
 
 inline int pad_up(int v, int m) { return (v + m - 1) / m * m; }
 // Padded Chebyshev order: 16, 32, 48, 64, 96 or 128.
@@ -69,8 +71,8 @@ struct Views {
   double* Dp;            // [3][RZ or RG][nqt*KS][NJ] k-side partials: gluon-a | gluon-b | ghost-a
   double* Pip;           // [RZ + RG][nqt*KS][2] partial self-energies (sum, rounding error)
   double* Absp;          // [RZ + RG][nqt*KS] partial sums of |integrand|
-  double* Eq;            // [Rbp][NJ] B . T (+ k-side sums for the gluon rows)
-  double* Dgh;           // [RG][NJ] k-side sums of the ghost rows (target a)
+  double* Eq;            // [kCS][Rbp][NJ] B . T (+ k-side sums for the gluon rows), by part
+  double* Dgh;           // [kCS][RG][NJ] k-side sums of the ghost rows (target a), by part
   double* rw;            // [RZ + RG] row weights of a vector-Jacobian product
   // Newton
   double* LU;            // [np][np+1], np = 16 ceil(n/16): padded factors of [A | b] when they do not fit LDS

@@ -479,48 +479,54 @@ __global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
 }
 
 // --------------------------------------------------------------------------
-// Eq = B . T on the FP64 matrix cores, plus the k-side sums.  Blocks with
-// blockIdx.x < Rbp/16 compute one 16 x 16 tile of Eq (the four waves split
-// the radial sum and meet in LDS) and add, for gluon rows, the k-side partial
-// sums of the same target; the remaining blocks reduce the ghost rows'
-// k-side partials into Dgh.  Every sum runs in a fixed order.
+// Eq = B . T on the FP64 matrix cores, plus the k-side sums, in kCS parts:
+// part p takes the radial nodes [p Qp/kCS, (p+1) Qp/kCS) and the partial
+// tiles [p ntile/kCS, (p+1) ntile/kCS) and writes Eq[p] (the assembly adds the
+// parts in a fixed order).  Splitting the sum keeps few dependent loads per
+// wave: the operands were written by other XCDs and come from beyond the L2.
+// Blocks with bx < Rbp/16 compute one 16 x 16 tile (the four waves split the
+// part's radial range and meet in LDS) and add, for gluon rows, the k-side
+// partial sums of the same target; the remaining blocks reduce the ghost
+// rows' k-side partials into Dgh[p].
 template <bool MIX>
-__device__ __forceinline__ void contract_body(const Views& v, int bx, int by) {
+__device__ __forceinline__ void contract_body(const Views& v, int bx, int by, int part) {
   using acc_t = typename std::conditional<MIX, float, double>::type;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int Qp = v.Qp, NJ = v.NJ;
   const int ntile = v.nqt * v.KS;
+  const int tlo = part * ntile / kCS, thi = (part + 1) * ntile / kCS;
   const size_t dstride = (size_t)ntile * NJ;
   const int ntiles_r = v.Rbp / 16;
   const acc_t* __restrict__ Dp = reinterpret_cast<const acc_t*>(v.Dp);
   if (bx >= ntiles_r) {
-    // ghost rows, k-side (target a): Dgh[row][j] = sum over tiles
+    // ghost rows, k-side (target a): Dgh[part][row][j] = sum over the part's tiles
     const int row0 = (bx - ntiles_r) * 16;
     const acc_t* D = Dp + (size_t)2 * v.RZ * dstride;
+    acc_t* out = reinterpret_cast<acc_t*>(v.Dgh) + (size_t)part * v.RG * NJ;
     for (int e = t; e < 16 * 16; e += 256) {
       const int r = row0 + (e >> 4), j = by * 16 + (e & 15);
       if (r < v.RG) {
         const acc_t* src = D + (size_t)r * dstride + j;
         acc_t sum = 0;
 #pragma unroll 4
-        for (int k = 0; k < ntile; ++k) sum += src[(size_t)k * NJ];
-        reinterpret_cast<acc_t*>(v.Dgh)[(size_t)r * NJ + j] = sum;
+        for (int k = tlo; k < thi; ++k) sum += src[(size_t)k * NJ];
+        out[(size_t)r * NJ + j] = sum;
       }
     }
     return;
   }
   const int r0 = bx * 16, j0 = by * 16;
-  const int qper = Qp / 4;
-  const int qbeg = wave * qper;
+  const int qper = Qp / kCS / 4;
+  const int qbeg = part * (Qp / kCS) + wave * qper;
   const int i = lane & 15, kk = lane >> 4;
   const acc_t* A = reinterpret_cast<const acc_t*>(v.Bm) + (size_t)(r0 + i) * Qp + kk;
   const size_t kstride = (size_t)v.Rbp * Qp;  // angular slices of B
-  __shared__ acc_t part[4][4][64];
+  __shared__ acc_t part_[4][4][64];
   if constexpr (MIX) {
     typedef float f4 __attribute__((ext_vector_type(4)));
     f4 acc = {0.f, 0.f, 0.f, 0.f};
     const float* B = v.Ttab32 + (size_t)kk * NJ + j0 + i;
-#pragma unroll 4
+#pragma unroll 8
     for (int q = qbeg; q < qbeg + qper; q += 4) {
       float a = A[q];
       for (int k = 1; k < v.KS; ++k) a += A[k * kstride + q];
@@ -528,12 +534,12 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by) {
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
+    for (int r = 0; r < 4; ++r) part_[wave][r][lane] = acc[r];
   } else {
     typedef double d4 __attribute__((ext_vector_type(4)));
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     const double* B = v.Ttab + (size_t)kk * NJ + j0 + i;
-#pragma unroll 4
+#pragma unroll 8
     for (int q = qbeg; q < qbeg + qper; q += 4) {
       double a = A[q];
       for (int k = 1; k < v.KS; ++k) a += A[k * kstride + q];
@@ -541,7 +547,7 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by) {
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
+    for (int r = 0; r < 4; ++r) part_[wave][r][lane] = acc[r];
   }
   __syncthreads();
   {
@@ -551,21 +557,23 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by) {
     const int ri = t >> 4, cj = t & 15;
     const int l = MIX ? (ri >> 2) * 16 + cj : (ri & 3) * 16 + cj;
     const int rg = MIX ? (ri & 3) : (ri >> 2);
-    acc_t sum = ((part[0][rg][l] + part[1][rg][l]) + part[2][rg][l]) + part[3][rg][l];
+    acc_t sum = ((part_[0][rg][l] + part_[1][rg][l]) + part_[2][rg][l]) + part_[3][rg][l];
     const int row = r0 + ri, col = j0 + cj;
     if (row < 2 * v.RZ) {  // gluon rows: add the k-side sums of the same target
       const acc_t* src = Dp + (size_t)row * dstride + col;  // groups a, b are contiguous
       acc_t ds_ = 0;
 #pragma unroll 4
-      for (int k = 0; k < ntile; ++k) ds_ += src[(size_t)k * NJ];
+      for (int k = tlo; k < thi; ++k) ds_ += src[(size_t)k * NJ];
       sum += ds_;
     }
-    reinterpret_cast<acc_t*>(v.Eq)[(size_t)row * NJ + col] = sum;
+    reinterpret_cast<acc_t*>(v.Eq)[((size_t)part * v.Rbp + row) * NJ + col] = sum;
   }
 }
 
 template <bool MIX>
-__global__ __launch_bounds__(256) void contract_kernel(Views v) { contract_body<MIX>(v, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(256) void contract_kernel(Views v) {
+  contract_body<MIX>(v, blockIdx.x, blockIdx.y, blockIdx.z);
+}
 
 
 // --------------------------------------------------------------------------
@@ -611,12 +619,21 @@ __global__ __launch_bounds__(256) void residual_rows_kernel(Views v, Phys ph, do
 }
 
 // J row r = one block.  MIX: Eq and Dgh hold FP32 sums.
+template <typename T>
+__device__ __forceinline__ double sum_parts(const T* p, size_t stride) {
+  double s_ = (double)p[0];
+#pragma unroll
+  for (int q = 1; q < kCS; ++q) s_ += (double)p[q * stride];
+  return s_;
+}
+
 template <bool MIX>
 __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, int r, double* __restrict__ J,
                                               double* F, double* S) {
   using acc_t = typename std::conditional<MIX, float, double>::type;
   const acc_t* __restrict__ Eq = reinterpret_cast<const acc_t*>(v.Eq);
   const acc_t* __restrict__ Dgh = reinterpret_cast<const acc_t*>(v.Dgh);
+  const size_t es = (size_t)v.Rbp * v.NJ, gs = (size_t)v.RG * v.NJ;  // part strides
   const int t = threadIdx.x;
   const int NJ = v.NJ, n = v.n;
   const bool gl = r < v.n_z;
@@ -631,10 +648,10 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
     for (int c = t; c < n; c += 256) {
       double val;
       if (c < v.n_z) {
-        val = -d * Tx[c] - (double)Ea[(size_t)i * NJ + c] + (double)Ea[(size_t)sub * NJ + c];
+        val = -d * Tx[c] - sum_parts(Ea + (size_t)i * NJ + c, es) + sum_parts(Ea + (size_t)sub * NJ + c, es);
       } else {
         const int j = c - v.n_z;
-        val = -(double)Eb[(size_t)i * NJ + j] + (double)Eb[(size_t)sub * NJ + j];
+        val = -sum_parts(Eb + (size_t)i * NJ + j, es) + sum_parts(Eb + (size_t)sub * NJ + j, es);
       }
       Jr[c] = val;
     }
@@ -644,10 +661,10 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
     for (int c = t; c < n; c += 256) {
       double val;
       if (c < v.n_z) {
-        val = -(double)Dgh[(size_t)i * NJ + c] + (double)Dgh[(size_t)sub * NJ + c];
+        val = -sum_parts(Dgh + (size_t)i * NJ + c, gs) + sum_parts(Dgh + (size_t)sub * NJ + c, gs);
       } else {
         const int j = c - v.n_z;
-        val = -d * Tx[j] - (double)Eb[(size_t)i * NJ + j] + (double)Eb[(size_t)sub * NJ + j];
+        val = -d * Tx[j] - sum_parts(Eb + (size_t)i * NJ + j, es) + sum_parts(Eb + (size_t)sub * NJ + j, es);
       }
       Jr[c] = val;
     }
@@ -1197,13 +1214,15 @@ __global__ __launch_bounds__(256) void vjp_reduce_kernel(Views v, const double* 
       double s_ = 0.0;
       if (c < v.n_z) {
         const int j = c;
-        for (int r = 0; r < v.RZ; ++r) s_ += v.Eq[(size_t)r * NJ + j];
-        for (int r = 0; r < v.RG; ++r) s_ += v.Dgh[(size_t)r * NJ + j];
+        const size_t es = (size_t)v.Rbp * NJ, gs = (size_t)v.RG * NJ;
+        for (int r = 0; r < v.RZ; ++r) s_ += sum_parts(v.Eq + (size_t)r * NJ + j, es);
+        for (int r = 0; r < v.RG; ++r) s_ += sum_parts(v.Dgh + (size_t)r * NJ + j, gs);
         for (int i = 0; i < v.n_z; ++i) s_ -= u[i] * exp(-v.lnX[i]) * v.Text[(size_t)i * NJ + j];
       } else {
         const int j = c - v.n_z;
-        for (int r = 0; r < v.RZ; ++r) s_ += v.Eq[(size_t)(v.RZ + r) * NJ + j];
-        for (int r = 0; r < v.RG; ++r) s_ += v.Eq[(size_t)(2 * v.RZ + r) * NJ + j];
+        const size_t es = (size_t)v.Rbp * NJ;
+        for (int r = 0; r < v.RZ; ++r) s_ += sum_parts(v.Eq + (size_t)(v.RZ + r) * NJ + j, es);
+        for (int r = 0; r < v.RG; ++r) s_ += sum_parts(v.Eq + (size_t)(2 * v.RZ + r) * NJ + j, es);
         for (int i = 0; i < v.n_g; ++i)
           s_ -= u[v.n_z + i] * exp(-v.lnX[v.n_z + i]) * v.Text[(size_t)(v.n_z + i) * NJ + j];
       }
@@ -1292,13 +1311,13 @@ __global__ __launch_bounds__(256) void batch_point_kernel(const SolveDesc* __res
 }
 
 __global__ __launch_bounds__(256) void batch_contract_kernel(const SolveDesc* __restrict__ d,
-                                                             const int* __restrict__ mask) {
+                                                             const int* __restrict__ mask, int nct) {
   const int b = blockIdx.z;
   if (!mask[b]) return;
   const Views& v = d[b].v;
-  const int bx = blockIdx.x, by = blockIdx.y;
+  const int bx = blockIdx.x, part = blockIdx.y / nct, by = blockIdx.y - part * nct;
   if (bx >= v.Rbp / 16 + (v.RG + 15) / 16 || by >= v.NJ / 16) return;
-  contract_body<false>(v, bx, by);
+  contract_body<false>(v, bx, by, part);
 }
 
 __global__ __launch_bounds__(256) void batch_assemble_kernel(const SolveDesc* __restrict__ d,
@@ -1421,7 +1440,7 @@ hipError_t launch_points(const Views& v, const Phys& ph, int mode, bool mix, hip
 
 hipError_t launch_contract(const Views& v, bool mix, hipStream_t st) {
   const int gh_blocks = (v.RG + 15) / 16;
-  const dim3 grid(v.Rbp / 16 + gh_blocks, v.NJ / 16);
+  const dim3 grid(v.Rbp / 16 + gh_blocks, v.NJ / 16, kCS);
   if (mix)
     hipLaunchKernelGGL(contract_kernel<true>, grid, dim3(256), 0, st, v);
   else
@@ -1583,8 +1602,8 @@ int batch_points_occupancy(int mode, int max_nj) {
 }
 
 hipError_t launch_batch_contract(const BatchArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(batch_contract_kernel, dim3(a.max_rbt, a.max_nj / 16, a.count), dim3(256), 0, st, a.desc,
-                     a.mask);
+  hipLaunchKernelGGL(batch_contract_kernel, dim3(a.max_rbt, kCS * (a.max_nj / 16), a.count), dim3(256), 0, st,
+                     a.desc, a.mask, a.max_nj / 16);
   return hipGetLastError();
 }
 

@@ -54,7 +54,8 @@ class NewtonReport(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("fnorm", C.c_double),
                 ("fnorm2", C.c_double), ("fnorm_hist", C.c_double * 128),
                 ("relax_hist", C.c_double * 128), ("n_jacobians", C.c_int32),
-                ("n_residuals", C.c_int32), ("t_total_ms", C.c_double)]
+                ("n_residuals", C.c_int32), ("t_total_ms", C.c_double),
+                ("n_jacobians_mixed", C.c_int32), ("reserved2_", C.c_int32)]
 
 
 class BatchTuning(C.Structure):
@@ -150,6 +151,7 @@ class NewtonResult:
     n_jacobians: int = 0
     n_residuals: int = 0
     t_total_ms: float = 0.0
+    n_jacobians_mixed: int = 0
 
 
 class Solver:
@@ -255,7 +257,7 @@ class Solver:
                             fnorm2=rep.fnorm2, fnorm_hist=list(rep.fnorm_hist[: rep.iters + 1]),
                             relax_hist=list(rep.relax_hist[: rep.iters]),
                             n_jacobians=rep.n_jacobians, n_residuals=rep.n_residuals,
-                            t_total_ms=rep.t_total_ms)
+                            t_total_ms=rep.t_total_ms, n_jacobians_mixed=rep.n_jacobians_mixed)
 
     def newton_step(self, c, rho: float = 1.0, out=None, check: bool = False):
         """One Newton iteration: returns (c_new, F(c_new), S(c_new)).  `out`

@@ -8,10 +8,13 @@ are in brackets):
   J    normwise ||J_mix - J_ref||_F <= 1e-5 ||J_ref||_F  [2.7e-7]
        per row max_c |J_mix - J_ref| <= 1e-3 max_c |J_ref|  [1.4e-4, N = 16 ghost rows;
        2.4e-6 at N = 64, 4.8e-6 at N = 128];
-  c*   Newton with the FP32 Newton matrix converges linearly to the root of the
-       FP64 residual: continued to its rounding floor it meets the FP64 bound
-       u || |J^{-1}| S ||_inf (twice: both sides at their floor);
-  iterations  N = 16: as FP64; N = 64: about twice FP64 (16 against 8).
+  c*   the Newton iteration uses FP32 matrices while a step at least halves
+       the merit and the scaled residual is above 1e-6, FP64 ones afterwards;
+       its root is that of the FP64 residual, within twice the FP64 bound
+       u || |J^{-1}| S ||_inf (both sides at their rounding floor).  With FP32
+       matrices alone the iteration at N = 64 sometimes stalls near 1e-2: the
+       ill-conditioning of the MOM-subtracted gluon rows (terms up to 1e8
+       cancel) amplifies the FP32 errors of the derivative sums.
 """
 import numpy as np
 import pytest
@@ -87,7 +90,8 @@ def test_mixed_newton_reaches_fp64_root(ref, dse, name):
     S = ref.residual_scale(p, cr)
     bound = 2.0 ** -53 * np.max(np.abs(np.linalg.inv(J)) @ S)
     err = np.max(np.abs(_np(r.c) - cr))
-    _note("%s mixed: iters %d (oracle FP64 %d), merit %.2e, coefficient diff %.2e, bound %.2e"
-          % (name, r.iters, rr["iters"], r.fnorm, err, bound))
+    _note("%s mixed: iters %d (%d FP32 matrices; oracle FP64 %d), merit %.2e, coefficient diff %.2e, bound %.2e"
+          % (name, r.iters, r.n_jacobians_mixed, rr["iters"], r.fnorm, err, bound))
     assert r.status == 0
+    assert r.n_jacobians_mixed >= 1
     assert err <= 2 * bound
