@@ -801,7 +801,6 @@ struct LUShared {
   int rmap[256];     // row position -> physical row
   double dinv[256];  // 1 / U[k][k]
   double wsv[256];   // staging of the transposed solve
-  double ub[LU_NB];  // pivot row broadcast
   int sing;
 };
 
@@ -835,16 +834,16 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
   for (int m = 1; m < MR; ++m)
     if (mp == m) { lsel = lpos[m]; psel = P[m][O]; }
   const int p = __builtin_amdgcn_readlane(lsel, lp);
-  const double inv = 1.0 / readlane_d(psel, lp);  // overlaps the broadcast below
-  // (the previous column's reads of ub precede these writes in every lane)
-  if (lane == lp) {
+  const double inv = 1.0 / readlane_d(psel, lp);
+  // the pivot row's remaining entries (CE - O - 1 of them, 7.5 on average over
+  // a panel), read across lanes from the lane that holds it
+  double rp[CE];
 #pragma unroll
-    for (int cc = O + 1; cc < CE; ++cc) {
-      double sel = P[0][cc];
+  for (int cc = O + 1; cc < CE; ++cc) {
+    double sel = P[0][cc];
 #pragma unroll
-      for (int m = 1; m < MR; ++m) if (mp == m) sel = P[m][cc];
-      sh.ub[cc] = sel;
-    }
+    for (int m = 1; m < MR; ++m) if (mp == m) sel = P[m][cc];
+    rp[cc] = readlane_d(sel, lp);
   }
   if (lane == 0) {
     sh.spiv[kc] = p;
@@ -857,10 +856,6 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
       else if (lpos[m] == p) lpos[m] = kc;
     }
   }
-  wave_memory_sync();
-  double rp[CE];
-#pragma unroll
-  for (int cc = O + 1; cc < CE; ++cc) rp[cc] = sh.ub[cc];
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     const bool below = lpos[m] > kc;
@@ -902,6 +897,105 @@ __device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR]
   }
 }
 
+// Loads the rows of the panel at k0 (positions k0 ..) into wave 0's registers
+// and factors it; lpos/phys return each register row's new position and its
+// physical row (the caller publishes them to the row map).
+template <int MR>
+__device__ __forceinline__ void lu_factor_panel(double* M, int ld, int np, const int* rmap, int k0, int lane,
+                                                LUShared& sh, int (&lpos)[MR], int (&phys)[MR], int& sg) {
+  double P[MR][LU_NB];
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const int pos = k0 + lane + 64 * m;
+    lpos[m] = pos < np ? pos : -1;  // -1: no row (never a candidate, never updated)
+    phys[m] = pos < np ? rmap[pos] : 0;
+#pragma unroll
+    for (int c = 0; c < LU_NB; ++c) P[m][c] = pos < np ? M[(size_t)phys[m] * ld + k0 + c] : 0.0;
+  }
+  sg = 0;
+  lu_panel<MR, 0>(P, lpos, phys, M, ld, lane, k0, sh, sg);
+}
+
+// U12 = L11^{-1} A12 for the columns [jc, jc + ncols) (ncols <= 16): lanes
+// 0 .. ncols-1 of the calling wave, one column each, column-oriented (step cc
+// subtracts L11[:, cc] u[cc] from the rows below: a dependency chain of 15).
+__device__ __forceinline__ void lu_u12_block(double* M, int ld, int k0, const int (&pr)[LU_NB], int jc, int ncols,
+                                             int lane) {
+  if (lane >= ncols) return;
+  const int j = jc + lane;
+  double u[LU_NB];
+#pragma unroll
+  for (int c = 0; c < LU_NB; ++c) u[c] = M[(size_t)pr[c] * ld + j];
+#pragma unroll
+  for (int cc = 0; cc < LU_NB - 1; ++cc) {
+#pragma unroll
+    for (int c = cc + 1; c < LU_NB; ++c) u[c] = fma(-M[(size_t)pr[c] * ld + k0 + cc], u[cc], u[c]);
+  }
+#pragma unroll
+  for (int c = 1; c < LU_NB; ++c) M[(size_t)pr[c] * ld + j] = u[c];
+}
+
+// A22[:, jc .. jc+15] -= L21 U12[:, jc .. jc+15] for tile rows below j0, by
+// one wave on the matrix cores, two tile rows per step: operands
+// A[i][k] = -L21 in lane i + 16 k, B[k][j] = U12 in lane j + 16 k, the tile as
+// accumulator (lane l, register r: row l/16 + 4 r, column l % 16).
+// Tile rows ti = t0, t0 + tstep, ... (each step takes ti and ti + 1).
+__device__ __forceinline__ void lu_trail_rows(double* M, int ld, const int* rmap, int k0, int j0, int nt, int jc,
+                                              const int (&brow)[4], int lane, int t0, int tstep) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int li = lane & 15, lk = lane >> 4;
+  if (t0 >= nt) return;
+  double bv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) bv[s] = M[(size_t)brow[s] * ld + jc + li];
+  for (int ti = t0; ti < nt; ti += tstep) {
+    const bool two = ti + 1 < nt;
+    const int i0 = j0 + 16 * ti, i1 = i0 + 16;
+    const int arow0 = rmap[i0 + li], arow1 = two ? rmap[i1 + li] : arow0;
+    int crow0[4], crow1[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      crow0[r] = rmap[i0 + lk + 4 * r];
+      crow1[r] = two ? rmap[i1 + lk + 4 * r] : crow0[r];
+    }
+    d4 acc0, acc1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc0[r] = M[(size_t)crow0[r] * ld + jc + li];
+      acc1[r] = two ? M[(size_t)crow1[r] * ld + jc + li] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double a0 = -M[(size_t)arow0 * ld + k0 + 4 * s + lk];
+      const double a1 = two ? -M[(size_t)arow1 * ld + k0 + 4 * s + lk] : 0.0;
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[s], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[s], acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      M[(size_t)crow0[r] * ld + jc + li] = acc0[r];
+      if (two) M[(size_t)crow1[r] * ld + jc + li] = acc1[r];
+    }
+  }
+}
+
+// Right-hand side, rows below j0: b2 -= L21 y1 (one wave, lanes over rows).
+__device__ __forceinline__ void lu_trail_rhs(double* M, int ld, const int* rmap, int k0, int j0, int np,
+                                             const int (&pr)[LU_NB], int lane) {
+  const int col = np;
+  double y1[LU_NB];
+#pragma unroll
+  for (int c = 0; c < LU_NB; ++c) y1[c] = M[(size_t)pr[c] * ld + col];
+  for (int i = j0 + lane; i < np; i += 64) {
+    const int pi_ = rmap[i];
+    const double* Li = M + (size_t)pi_ * ld + k0;
+    double s_ = M[(size_t)pi_ * ld + col];
+#pragma unroll
+    for (int c = 0; c < LU_NB; ++c) s_ = fma(-Li[c], y1[c], s_);
+    M[(size_t)pi_ * ld + col] = s_;
+  }
+}
+
 template <bool IN_LDS, int MR>
 __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, const double* __restrict__ b,
                                         double* x, double* __restrict__ Aglob, int* piv, int trans, int* flag,
@@ -914,25 +1008,28 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   double* M = IN_LDS ? lds : Aglob;
   __shared__ LUShared sh;
   const int* __restrict__ rmap = sh.rmap;
-  // load [A | b] padded with an identity block, 64 loads in flight per thread
+  // load [A | b] padded with an identity block: wave w takes rows w, w + 4,
+  // ..., lane l columns l, l + 64, ...; sixteen rows per batch
   {
-    const int tot = np * np;
-    for (int e0 = t; e0 < tot; e0 += 256 * 64) {
-      double v_[64];
+    const int ncu = (np + 63) / 64;  // column chunks of 64 (<= 4)
+    for (int r0 = wave; r0 < np; r0 += 4 * 16) {
+      double v_[16][4];
 #pragma unroll
-      for (int u = 0; u < 64; ++u) {
-        const int e = e0 + 256 * u;
-        const int r = e / np, c = e - r * np;
-        double val = (r == c) ? 1.0 : 0.0;
-        if (e < tot && r < n && c < n) val = Ain[(size_t)r * n + c];
-        v_[u] = val;
+      for (int rr = 0; rr < 16; ++rr) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + 4 * rr, c = lane + 64 * u;
+          double val = (r == c) ? 1.0 : 0.0;
+          if (u < ncu && r < n && c < n) val = Ain[(size_t)r * n + c];
+          v_[rr][u] = val;
+        }
       }
 #pragma unroll
-      for (int u = 0; u < 64; ++u) {
-        const int e = e0 + 256 * u;
-        if (e < tot) {
-          const int r = e / np, c = e - r * np;
-          M[(size_t)r * ld + c] = v_[u];
+      for (int rr = 0; rr < 16; ++rr) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + 4 * rr, c = lane + 64 * u;
+          if (u < ncu && r < np && c < np) M[(size_t)r * ld + c] = v_[rr][u];
         }
       }
     }
@@ -944,102 +1041,69 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   if (t == 0) sh.sing = 0;
   __syncthreads();
 
-  for (int k0 = 0; k0 < np; k0 += LU_NB) {
-    if (wave == 0) {
-      double P[MR][LU_NB];
-      int lpos[MR], phys[MR];
+  // Panel k+1 is factored while panel k's update of the other columns runs
+  // (one panel of lookahead).  Per panel: U12 of all column blocks (the four
+  // waves), the next panel's tile column (the four waves, tile rows dealt in
+  // pairs), then wave 0 factors the next panel while waves 1-3 update the
+  // remaining column blocks and the right-hand side.  The next panel's
+  // interchanges reach the row map only after the barrier, once nobody reads
+  // the old one.
+  int lpos[MR], phys[MR];
+  if (wave == 0) {
+    int sg;
+    lu_factor_panel<MR>(M, ld, np, rmap, 0, lane, sh, lpos, phys, sg);
+    if (sg && lane == 0) sh.sing = 1;
+    if (!sg) {
+      wave_memory_sync();
 #pragma unroll
-      for (int m = 0; m < MR; ++m) {
-        const int pos = k0 + lane + 64 * m;
-        lpos[m] = pos < np ? pos : -1;  // -1: no row (never a candidate, never updated)
-        phys[m] = pos < np ? rmap[pos] : 0;
-#pragma unroll
-        for (int c = 0; c < LU_NB; ++c) P[m][c] = pos < np ? M[(size_t)phys[m] * ld + k0 + c] : 0.0;
-      }
-      int sg = 0;
-      lu_panel<MR, 0>(P, lpos, phys, M, ld, lane, k0, sh, sg);
-      if (sg) {
-        if (lane == 0) sh.sing = 1;
-      } else {
-        wave_memory_sync();  // every lane has read rmap before it changes
-#pragma unroll
-        for (int m = 0; m < MR; ++m)
-          if (lpos[m] >= 0) sh.rmap[lpos[m]] = phys[m];
-      }
+      for (int m = 0; m < MR; ++m)
+        if (lpos[m] >= 0) sh.rmap[lpos[m]] = phys[m];
     }
-    __syncthreads();
-    if (sh.sing) break;
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < np && !sh.sing; k0 += LU_NB) {
     const int j0 = k0 + LU_NB;
-    // U12 = L11^{-1} A12: one column per thread, in registers, column-oriented
-    // (step cc subtracts L11[:, cc] u[cc] from the rows below: a dependency
-    // chain of 15 steps); after the last panel only the right-hand side is left
-    {
-      int pr[LU_NB];
+    int pr[LU_NB];  // physical rows of the panel's positions
 #pragma unroll
-      for (int c = 0; c < LU_NB; ++c) pr[c] = rmap[k0 + c];
-      for (int j = j0 + t; j < ncol; j += 256) {
-        double u[LU_NB];
+    for (int c = 0; c < LU_NB; ++c) pr[c] = rmap[k0 + c];
+    if (j0 >= np) {  // after the last panel only U12 of the right-hand side is left
+      if (wave == 0) lu_u12_block(M, ld, k0, pr, np, 1, lane);
+      __syncthreads();
+      break;
+    }
+    const int nblk = (np - j0) / 16;
+    int brow[4];
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) u[c] = M[(size_t)pr[c] * ld + j];
-#pragma unroll
-        for (int cc = 0; cc < LU_NB - 1; ++cc) {
-#pragma unroll
-          for (int c = cc + 1; c < LU_NB; ++c) u[c] = fma(-M[(size_t)pr[c] * ld + k0 + cc], u[cc], u[c]);
-        }
-#pragma unroll
-        for (int c = 1; c < LU_NB; ++c) M[(size_t)pr[c] * ld + j] = u[c];
+    for (int s = 0; s < 4; ++s) brow[s] = pr[4 * s + (lane >> 4)];
+    // U12: block 0 (the next panel's columns) by wave 0, the other blocks and
+    // the right-hand side dealt to waves 1-3
+    if (wave == 0) {
+      lu_u12_block(M, ld, k0, pr, j0, 16, lane);
+    } else {
+      for (int bk = wave; bk <= nblk; bk += 3) {
+        if (bk < nblk) lu_u12_block(M, ld, k0, pr, j0 + 16 * bk, 16, lane);
+        else lu_u12_block(M, ld, k0, pr, np, 1, lane);
       }
     }
     __syncthreads();
-    // A22 -= L21 U12 on the matrix cores: tile (ti, tj) of 16 x 16; operands
-    // A[i][k] = -L21 in lane i + 16 k, B[k][j] = U12 in lane j + 16 k, the
-    // tile itself as accumulator (lane l, register r: row l/16 + 4 r,
-    // column l % 16); two tiles of the same tile row per step
-    if (j0 < np) {
-      const int nt = (np - j0) / 16;
-      const int li = lane & 15, lk = lane >> 4;
-      int brow[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) brow[s] = rmap[k0 + 4 * s + lk];
-      const int npair = (nt + 1) / 2;
-      for (int e = wave; e < nt * npair; e += 4) {
-        const int ti = e / npair, tp = e - ti * npair;
-        const int i0 = j0 + 16 * ti;
-        const int c0 = j0 + 32 * tp, c1 = c0 + 16;
-        const bool two = c1 < np;
-        const int arow = rmap[i0 + li];
-        int crow[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) crow[r] = rmap[i0 + lk + 4 * r];
-        d4 acc0, acc1;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          acc0[r] = M[(size_t)crow[r] * ld + c0 + li];
-          acc1[r] = two ? M[(size_t)crow[r] * ld + c1 + li] : 0.0;
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double a = -M[(size_t)arow * ld + k0 + 4 * s + lk];
-          const double b0 = M[(size_t)brow[s] * ld + c0 + li];
-          const double b1 = two ? M[(size_t)brow[s] * ld + c1 + li] : 0.0;
-          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          M[(size_t)crow[r] * ld + c0 + li] = acc0[r];
-          if (two) M[(size_t)crow[r] * ld + c1 + li] = acc1[r];
-        }
+    // block 0's tile column by all four waves (tile rows dealt in pairs)
+    lu_trail_rows(M, ld, rmap, k0, j0, nblk, j0, brow, lane, 2 * wave, 8);
+    __syncthreads();
+    if (wave == 0) {
+      int sg;
+      lu_factor_panel<MR>(M, ld, np, rmap, j0, lane, sh, lpos, phys, sg);
+      if (sg && lane == 0) sh.sing = 1;
+    } else {
+      for (int bk = wave; bk <= nblk; bk += 3) {  // bk == nblk: the right-hand side
+        if (bk < nblk) lu_trail_rows(M, ld, rmap, k0, j0, nblk, j0 + 16 * bk, brow, lane, 0, 2);
+        else lu_trail_rhs(M, ld, rmap, k0, j0, np, pr, lane);
       }
-      // right-hand-side column
-      for (int i = j0 + t; i < np; i += 256) {
-        const int pi_ = rmap[i];
-        const double* Li = M + (size_t)pi_ * ld + k0;
-        double s_ = M[(size_t)pi_ * ld + np];
+    }
+    __syncthreads();
+    if (wave == 0 && !sh.sing) {
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) s_ = fma(-Li[c], M[(size_t)rmap[k0 + c] * ld + np], s_);
-        M[(size_t)pi_ * ld + np] = s_;
-      }
+      for (int m = 0; m < MR; ++m)
+        if (lpos[m] >= 0) sh.rmap[lpos[m]] = phys[m];
     }
     __syncthreads();
   }
