@@ -7,7 +7,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -209,10 +211,17 @@ size_t layout(const dse_params& p, Views* v, char* base, int ks) {
   t.RZ = p.n_z + 1;
   t.RG = p.n_g + 1;
   t.nqt = t.Qp / 64;
-  // angular slices: enough blocks to fill the chip (about four per CU for the
-  // larger row kind), at least two angles per lane
-  t.KS = 1;
-  while (t.KS < 8 && (t.RZ > t.RG ? t.RZ : t.RG) * t.nqt * t.KS < 1024 && t.Kp / (4 * t.KS * 2) >= 2) t.KS *= 2;
+  // angular slices: the block count of the larger row kind closest to 1024
+  // (about four blocks per CU), at most eight slices and at least two angles
+  // per wave.  Fewer, longer blocks win over a power of two that overshoots:
+  // each wave's set-up and reductions are paid once per block.
+  {
+    const int per_slice = (t.RZ > t.RG ? t.RZ : t.RG) * t.nqt;
+    const int kmax = std::max(1, std::min(8, t.Kp / 8));
+    t.KS = 1;
+    for (int k = 2; k <= kmax; ++k)
+      if (std::abs(per_slice * k - 1024) < std::abs(per_slice * t.KS - 1024)) t.KS = k;
+  }
   if (ks > 0) t.KS = ks;
   t.Rb = 2 * t.RZ + t.RG;
   t.Rbp = pad_up(t.Rb, 16);

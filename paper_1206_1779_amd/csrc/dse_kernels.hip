@@ -190,9 +190,9 @@ __device__ __forceinline__ void slice_reduce(T* vals, int lane, int& base, bool&
 enum { MODE_RES = 0, MODE_JAC = 1, MODE_VJP = 2, MODE_VTH = 3 };
 
 // LDS of one point-kernel block (doubles): red[3][4] at 0, bs[2][4][64] at 16,
-// ds[4][NT*NJ] at 528, the coefficients a | b at 528 + 8 NJ.
+// ds[4][NT*NJ] at 528.
 template <int NJ>
-__host__ __device__ constexpr int point_smem() { return 528 + 10 * NJ; }
+__host__ __device__ constexpr int point_smem() { return 528 + 8 * NJ; }
 
 template <int KIND, int NJ, int MODE, bool MIX = false>
 __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int row, int tile,
@@ -241,12 +241,11 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     pref = -ph.C * W * y;
   }
 
-  // coefficients in LDS: every angle re-reads them with broadcast loads (held
-  // in scalar registers they do not fit beside the uniform constants and end
-  // up parked in vector-register lanes, read back one half at a time)
-  double* __restrict__ cl = smem + 528 + 8 * NJ;
-  for (int j = t; j < 2 * NJ; j += 256) cl[j] = v.coef[j];
-  __syncthreads();
+  // Chebyshev coefficients a | b: wave-uniform, read a chunk at a time inside
+  // the recurrence through the scalar cache (scalar loads into scalar
+  // registers, no LDS traffic); the chunk loop stays a loop, so they are
+  // neither held in registers across it nor gathered at its top
+  const double* __restrict__ coef = v.coef;
   const double* __restrict__ ang = v.ang;
   const int Kp = v.Kp;
   const double rw = WEIGHTED ? v.rw[growrow] : 1.0;
@@ -261,8 +260,6 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   const int member = lane & (G - 1);
 
   for (int k = ks * 4 + wave; k < Kp; k += 4 * KS) {
-    const double* __restrict__ cal = cl;
-    const double* __restrict__ cbl = cl + NJ;
     const double ck = ang[k];
     const double s2h = ang[Kp + k];
     const double wk = KIND == GLUON ? ang[2 * Kp + k] : ang[3 * Kp + k];
@@ -274,28 +271,19 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     s = fmin(fmax(s, -1.0), 1.0);
     const double s2 = s + s;
 
-    // ---- pass 1: recurrence and series.  The coefficients are wave-uniform
-    // and read from LDS a chunk at a time; the chunk loop stays a loop, so they
-    // are neither held in registers across it nor gathered at its top.
+    // ---- pass 1: recurrence and series
     double sa = 0.0, sb = 0.0;
     double Tp = s, Tc = 1.0;  // (T_{-1}, T_0)
     double stp[G > 1 ? G : 1], stc[G > 1 ? G : 1];
-    // chunk width: a divisor of the pass-2 slice width JT, so that every start
-    // pair falls on a chunk boundary
-    constexpr int CH = (G == 1 || JT % 8 == 0) ? 8 : 4;
-    static_assert(NJ % CH == 0 && (G == 1 || JT % CH == 0), "chunks must tile the slices");
-#pragma clang loop unroll(disable)
-    for (int j0 = 0; j0 < NJ; j0 += CH) {
-      if (G > 1 && (j0 % JT) == 0) {  // start pairs (T_{m JT - 1}, T_{m JT}) of pass 2
-#pragma unroll
-        for (int m = 0; m < G; ++m)
-          if (m * JT == j0) { stp[m] = Tp; stc[m] = Tc; }
-      }
+    // chunk width: a divisor of the pass-2 slice width JT
+    constexpr int CH = JT % 8 == 0 ? 8 : 4;
+    static_assert(JT % CH == 0, "chunks must tile the slices");
+    auto chunk = [&](int j0) {
       double c8a[CH], c8b[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
-        c8a[u] = cal[j0 + u];
-        c8b[u] = KIND == GLUON ? cbl[j0 + u] : 0.0;
+        c8a[u] = coef[j0 + u];
+        c8b[u] = KIND == GLUON ? coef[NJ + j0 + u] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
@@ -305,8 +293,27 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
         Tp = Tc;
         Tc = Tn;
       }
+    };
+    // start pairs (T_{m JT - 1}, T_{m JT}) of pass 2.  Up to two slices: a
+    // uniform branch in the one chunk loop saves the second.  More: one chunk
+    // loop per slice, each pair saved into its fixed registers before it (a
+    // branch over several targets would become selects run on every chunk).
+    stp[0] = Tp;
+    stc[0] = Tc;
+    if constexpr (G > 2) {
+#pragma unroll
+      for (int m = 0; m < G; ++m) {
+        if (m > 0) { stp[m] = Tp; stc[m] = Tc; }
+#pragma clang loop unroll(disable)
+        for (int j0 = m * JT; j0 < (m + 1) * JT; j0 += CH) chunk(j0);
+      }
+    } else {
+#pragma clang loop unroll(disable)
+      for (int j0 = 0; j0 < NJ; j0 += CH) {
+        if (G == 2 && j0 == JT) { stp[G - 1] = Tp; stc[G - 1] = Tc; }
+        chunk(j0);
+      }
     }
-    if (G == 1) { stp[0] = s; stc[0] = 1.0; }
     double XZ = 0.0, XG = 0.0, dXa = 0.0;  // dXa: d ln(1 + omega l) / d alpha (UV)
     if (lz < ph.ln_eps2) {
       XZ = 2.0 * ph.kappa * (lz - ph.ln_eps2);
