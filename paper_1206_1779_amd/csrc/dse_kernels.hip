@@ -476,9 +476,15 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   }
 }
 
-// One block per (row, tile): blockIdx.x = row * (nqt KS) + tile.
+// One block per (row, tile): blockIdx.x = row * (nqt KS) + tile.  The gluon
+// rows' FP64 Jacobian kernel up to order 64 is held to three waves per SIMD
+// (168 VGPRs, no spills) instead of the two its free allocation gives.
 template <int KIND, int NJ, int MODE, bool MIX>
-__global__ __launch_bounds__(256) void point_kernel(Views v, Phys ph) {
+constexpr int point_waves() { return KIND == GLUON && MODE == MODE_JAC && !MIX && NJ <= 64 ? 3 : 1; }
+
+template <int KIND, int NJ, int MODE, bool MIX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(point_waves<KIND, NJ, MODE, MIX>())))
+void point_kernel(Views v, Phys ph) {
   __shared__ double smem[point_smem<NJ>()];
   const int ntile = v.nqt * v.KS;
   const int row = blockIdx.x / ntile;
@@ -750,7 +756,7 @@ __global__ void axpy_kernel(int n, const double* c, double rho, const double* d,
 //   panel    wave 0 holds the rows of the panel (MR per lane) in registers
 //            and factors it column by column: pivot = largest |a| (wave
 //            maximum by DPP; among equal maxima the first register row), the
-//            pivot row's entries broadcast through LDS, multipliers
+//            pivot row's entries read across lanes, multipliers
 //            a * (1 / pivot), rank-1 update.  Interchanges only change the
 //            logical positions of the register rows; at the end the panel's
 //            columns go back to their physical rows and rmap is updated;
@@ -1049,12 +1055,12 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   __syncthreads();
 
   // Panel k+1 is factored while panel k's update of the other columns runs
-  // (one panel of lookahead).  Per panel: U12 of all column blocks (the four
-  // waves), the next panel's tile column (the four waves, tile rows dealt in
-  // pairs), then wave 0 factors the next panel while waves 1-3 update the
-  // remaining column blocks and the right-hand side.  The next panel's
-  // interchanges reach the row map only after the barrier, once nobody reads
-  // the old one.
+  // (one panel of lookahead).  Per panel: U12 of the next panel's columns
+  // (and of one more block per other wave), the next panel's tile column
+  // (the four waves, tile rows dealt in pairs), then wave 0 factors the next
+  // panel while waves 1-3 finish U12 and update the remaining column blocks
+  // and the right-hand side.  The next panel's interchanges reach the row
+  // map only after the barrier, once nobody reads the old one.
   int lpos[MR], phys[MR];
   if (wave == 0) {
     int sg;
@@ -1082,15 +1088,14 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
     int brow[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) brow[s] = pr[4 * s + (lane >> 4)];
-    // U12: block 0 (the next panel's columns) by wave 0, the other blocks and
-    // the right-hand side dealt to waves 1-3
+    // U12 of block 0 (the next panel's columns) by wave 0; waves 1-3 take
+    // the first of their blocks (column blocks bk = wave, wave + 3, ...;
+    // bk == nblk is the right-hand side) here and the rest after the barrier
     if (wave == 0) {
       lu_u12_block(M, ld, k0, pr, j0, 16, lane);
-    } else {
-      for (int bk = wave; bk <= nblk; bk += 3) {
-        if (bk < nblk) lu_u12_block(M, ld, k0, pr, j0 + 16 * bk, 16, lane);
-        else lu_u12_block(M, ld, k0, pr, np, 1, lane);
-      }
+    } else if (wave <= nblk) {
+      if (wave < nblk) lu_u12_block(M, ld, k0, pr, j0 + 16 * wave, 16, lane);
+      else lu_u12_block(M, ld, k0, pr, np, 1, lane);
     }
     __syncthreads();
     // block 0's tile column by all four waves (tile rows dealt in pairs)
@@ -1101,9 +1106,22 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       lu_factor_panel<MR>(M, ld, np, rmap, j0, lane, sh, lpos, phys, sg);
       if (sg && lane == 0) sh.sing = 1;
     } else {
-      for (int bk = wave; bk <= nblk; bk += 3) {  // bk == nblk: the right-hand side
-        if (bk < nblk) lu_trail_rows(M, ld, rmap, k0, j0, nblk, j0 + 16 * bk, brow, lane, 0, 2);
-        else lu_trail_rhs(M, ld, rmap, k0, j0, np, pr, lane);
+      // a block's U12 rows, written by lanes 0-15, are read by every lane of
+      // the same wave in its update: the fence orders them
+      for (int bk = wave; bk <= nblk; bk += 3) {
+        if (bk < nblk) {
+          if (bk > 3) {
+            lu_u12_block(M, ld, k0, pr, j0 + 16 * bk, 16, lane);
+            wave_memory_sync();
+          }
+          lu_trail_rows(M, ld, rmap, k0, j0, nblk, j0 + 16 * bk, brow, lane, 0, 2);
+        } else {
+          if (bk > 3) {
+            lu_u12_block(M, ld, k0, pr, np, 1, lane);
+            wave_memory_sync();
+          }
+          lu_trail_rhs(M, ld, rmap, k0, j0, np, pr, lane);
+        }
       }
     }
     __syncthreads();
@@ -1134,36 +1152,31 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       const int r = lane + 64 * m;
       w[m] = r < np ? M[(size_t)prow[m] * ld + np] : 0.0;  // = L^{-1} P b
     }
-    // U x = y by blocks of 16 rows from the bottom: solve the diagonal block
-    // (values broadcast by lane reads), then update the rows above
+    // U x = y by blocks of 16 rows from the bottom.  The diagonal block's 16
+    // lanes (register row mi, lanes lb ..) work on one value wb: step cc reads
+    // x = wb[lb + cc] / U[cc][cc] across lanes and subtracts U[:, cc] x from
+    // every lane (lanes already solved keep their x in xv); then the rows
+    // above subtract the block's columns times x.
     for (int i1 = np; i1 > 0; i1 -= LU_NB) {
       const int i0 = i1 - LU_NB;
-      const int mi = i0 >> 6;
-      double xb[LU_NB], ub[MR][LU_NB], dv[LU_NB];
+      const int mi = i0 >> 6, lb = i0 & 63;
+      double wb = w[0];
+      int pb = prow[0];
 #pragma unroll
-      for (int cc = 0; cc < LU_NB; ++cc) dv[cc] = sh.dinv[i0 + cc];
+      for (int m = 1; m < MR; ++m)
+        if (mi == m) { wb = w[m]; pb = prow[m]; }
+      double ub[LU_NB], dv[LU_NB], xb[LU_NB];
 #pragma unroll
-      for (int m = 0; m < MR; ++m) {
-        const int r = lane + 64 * m;
-        const bool in = r >= i0 && r < i1;
-        const double* Ur = M + (size_t)prow[m] * ld + i0;
-#pragma unroll
-        for (int cc = 0; cc < LU_NB; ++cc) ub[m][cc] = in ? Ur[cc] : 0.0;
+      for (int cc = 0; cc < LU_NB; ++cc) {
+        ub[cc] = M[(size_t)pb * ld + i0 + cc];
+        dv[cc] = sh.dinv[i0 + cc];
       }
+      double xv = 0.0;
 #pragma unroll
       for (int cc = LU_NB - 1; cc >= 0; --cc) {
-        const int i = i0 + cc;
-        double sel = w[0];
-#pragma unroll
-        for (int m = 1; m < MR; ++m) if (mi == m) sel = w[m];
-        const double xi = readlane_d(sel, i & 63) * dv[cc];
-        xb[cc] = xi;
-#pragma unroll
-        for (int m = 0; m < MR; ++m) {
-          const int r = lane + 64 * m;
-          if (r == i) w[m] = xi;
-          else if (r >= i0 && r < i) w[m] = fma(-ub[m][cc], xi, w[m]);
-        }
+        xb[cc] = readlane_d(wb, lb + cc) * dv[cc];
+        xv = lane == lb + cc ? xb[cc] : xv;
+        wb = fma(-ub[cc], xb[cc], wb);
       }
 #pragma unroll
       for (int m = 0; m < MR; ++m) {
@@ -1174,6 +1187,8 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
 #pragma unroll
           for (int cc = 0; cc < LU_NB; ++cc) s_ = fma(-Ur[cc], xb[cc], s_);
           w[m] = s_;
+        } else if (r < i1) {
+          w[m] = xv;
         }
       }
     }
