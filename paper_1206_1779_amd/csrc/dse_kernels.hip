@@ -190,11 +190,11 @@ __device__ __forceinline__ void slice_reduce(T* vals, int lane, int& base, bool&
 enum { MODE_RES = 0, MODE_JAC = 1, MODE_VJP = 2, MODE_VTH = 3 };
 
 // LDS of one point-kernel block (doubles): red[3][4] at 0, bs[2][4][64] at 16,
-// ds[4][NT*NJ] at 528.
-template <int NJ>
-__host__ __device__ constexpr int point_smem() { return 528 + 8 * NJ; }
+// ds[4][NT*NJ] at 528; with CLDS the coefficients a | b at 528 + 8 NJ.
+template <int NJ, bool CLDS>
+__host__ __device__ constexpr int point_smem() { return 528 + (CLDS ? 10 : 8) * NJ; }
 
-template <int KIND, int NJ, int MODE, bool MIX = false>
+template <int KIND, int NJ, int MODE, bool MIX = false, bool CLDS = false>
 __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int row, int tile,
                                            double* __restrict__ smem) {
   using TL = Tile<KIND, NJ>;
@@ -242,10 +242,18 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   }
 
   // Chebyshev coefficients a | b: wave-uniform, read a chunk at a time inside
-  // the recurrence through the scalar cache (scalar loads into scalar
-  // registers, no LDS traffic); the chunk loop stays a loop, so they are
-  // neither held in registers across it nor gathered at its top
+  // the recurrence; the chunk loop stays a loop, so they are neither held in
+  // registers across it nor gathered at its top.  Read through the scalar
+  // cache into scalar registers (no LDS traffic), or, with CLDS (the batch
+  // kernel, whose many bodies leave no scalar registers to spare), staged in
+  // LDS and read with broadcast loads.
   const double* __restrict__ coef = v.coef;
+  if constexpr (CLDS) {
+    double* __restrict__ cl = smem + 528 + 8 * NJ;
+    for (int j = t; j < 2 * NJ; j += 256) cl[j] = v.coef[j];
+    __syncthreads();
+    coef = cl;
+  }
   const double* __restrict__ ang = v.ang;
   const int Kp = v.Kp;
   const double rw = WEIGHTED ? v.rw[growrow] : 1.0;
@@ -485,7 +493,7 @@ constexpr int point_waves() { return KIND == GLUON && MODE == MODE_JAC && !MIX &
 template <int KIND, int NJ, int MODE, bool MIX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(point_waves<KIND, NJ, MODE, MIX>())))
 void point_kernel(Views v, Phys ph) {
-  __shared__ double smem[point_smem<NJ>()];
+  __shared__ double smem[point_smem<NJ, false>()];
   const int ntile = v.nqt * v.KS;
   const int row = blockIdx.x / ntile;
   point_body<KIND, NJ, MODE, MIX>(v, ph, row, blockIdx.x - row * ntile, smem);
@@ -1360,7 +1368,7 @@ __global__ __launch_bounds__(256) void batch_point_kernel(const SolveDesc* __res
                                                           const int* __restrict__ mask,
                                                           const int4* __restrict__ items, int n_items,
                                                           int* counter, int persistent) {
-  __shared__ double smem[point_smem<NJMAX>()];
+  __shared__ double smem[point_smem<NJMAX, true>()];
   __shared__ int s_item;
   int it = blockIdx.x;
   for (;;) {
@@ -1379,8 +1387,8 @@ __global__ __launch_bounds__(256) void batch_point_kernel(const SolveDesc* __res
 #define DSE_BATCH_CASE(N)                                                                   \
   if constexpr (N <= NJMAX) {                                                               \
     if (nj == N) {                                                                          \
-      if (kind == GLUON) point_body<GLUON, N, MODE>(sd.v, sd.ph, row, tile, smem);          \
-      else point_body<GHOST, N, MODE>(sd.v, sd.ph, row, tile, smem);                        \
+      if (kind == GLUON) point_body<GLUON, N, MODE, false, true>(sd.v, sd.ph, row, tile, smem); \
+      else point_body<GHOST, N, MODE, false, true>(sd.v, sd.ph, row, tile, smem);           \
     }                                                                                       \
   }
       DSE_BATCH_CASE(16)
