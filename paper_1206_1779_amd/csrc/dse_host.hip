@@ -675,8 +675,7 @@ dse_status enqueue_step(dse_ctx* ctx, const double* c, double rho, double* c_new
   dse_status s = eval_jacobian(ctx, c, v.J, v.F, v.S);
   ctx->timing = timing;
   if (s != DSE_OK) return s;
-  HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, ctx->st));
-  HIP_TRY(ctx, dse::launch_axpy(v.n, c, rho, v.dlt, c_new, ctx->st));
+  HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, ctx->st, c, rho, c_new));  // and c_new = c - rho Delta
   return eval_residual(ctx, c_new, F_new, S_new ? S_new : v.St);
 }
 

@@ -124,8 +124,10 @@ hipError_t launch_norms(const Views& v, const double* F, const double* S, const 
                         double* out, hipStream_t st);
 hipError_t launch_axpy(int n, const double* c, double rho, const double* d, double* out,
                        hipStream_t st);
+// With cout != nullptr the solve also writes the update cout = cin - rho x.
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x,
-                           int trans, hipStream_t st);
+                           int trans, hipStream_t st, const double* cin = nullptr, double rho = 0.0,
+                           double* cout = nullptr);
 void lu_setup();  // LDS attributes of the factorisation kernels (call before any capture)
 
 // Batched family (one launch per stage for all problems whose mask entry is

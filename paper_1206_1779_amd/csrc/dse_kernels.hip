@@ -749,7 +749,7 @@ __global__ __launch_bounds__(256) void norms_kernel(int n, const double* F, cons
 
 __global__ void axpy_kernel(int n, const double* c, double rho, const double* d, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = c[i] - rho * d[i];
+  if (i < n) out[i] = fma(-rho, d[i], c[i]);
 }
 
 // --------------------------------------------------------------------------
@@ -920,18 +920,28 @@ __device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR]
 
 // Loads the rows of the panel at k0 (positions k0 ..) into wave 0's registers
 // and factors it; lpos/phys return each register row's new position and its
-// physical row (the caller publishes them to the row map).
-template <int MR>
+// physical row (the caller publishes them to the row map).  FIRST: the panel
+// at 0, read straight from the n x n input (identity padding, identity row
+// map) instead of from M.
+template <int MR, bool FIRST>
 __device__ __forceinline__ void lu_factor_panel(double* M, int ld, int np, const int* rmap, int k0, int lane,
-                                                LUShared& sh, int (&lpos)[MR], int (&phys)[MR], int& sg) {
+                                                LUShared& sh, int (&lpos)[MR], int (&phys)[MR], int& sg,
+                                                const double* __restrict__ Ain = nullptr, int n = 0) {
   double P[MR][LU_NB];
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     const int pos = k0 + lane + 64 * m;
     lpos[m] = pos < np ? pos : -1;  // -1: no row (never a candidate, never updated)
-    phys[m] = pos < np ? rmap[pos] : 0;
+    if (FIRST) {
+      phys[m] = pos < np ? pos : 0;
 #pragma unroll
-    for (int c = 0; c < LU_NB; ++c) P[m][c] = pos < np ? M[(size_t)phys[m] * ld + k0 + c] : 0.0;
+      for (int c = 0; c < LU_NB; ++c)
+        P[m][c] = pos < n && c < n ? Ain[(size_t)pos * n + c] : (pos == c ? 1.0 : 0.0);
+    } else {
+      phys[m] = pos < np ? rmap[pos] : 0;
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) P[m][c] = pos < np ? M[(size_t)phys[m] * ld + k0 + c] : 0.0;
+    }
   }
   sg = 0;
   lu_panel<MR, 0>(P, lpos, phys, M, ld, lane, k0, sh, sg);
@@ -1017,10 +1027,12 @@ __device__ __forceinline__ void lu_trail_rhs(double* M, int ld, const int* rmap,
   }
 }
 
+// With cout != nullptr the Newton update cout = cin - rho x is written beside x.
 template <bool IN_LDS, int MR>
 __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, const double* __restrict__ b,
                                         double* x, double* __restrict__ Aglob, int* piv, int trans, int* flag,
-                                        double* lds) {
+                                        double* lds, const double* __restrict__ cin = nullptr, double rho = 0.0,
+                                        double* __restrict__ cout = nullptr) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
@@ -1029,39 +1041,11 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   double* M = IN_LDS ? lds : Aglob;
   __shared__ LUShared sh;
   const int* __restrict__ rmap = sh.rmap;
-  // load [A | b] padded with an identity block: wave w takes rows w, w + 4,
-  // ..., lane l columns l, l + 64, ...; sixteen rows per batch
-  {
-    const int ncu = (np + 63) / 64;  // column chunks of 64 (<= 4)
-    for (int r0 = wave; r0 < np; r0 += 4 * 16) {
-      double v_[16][4];
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int r = r0 + 4 * rr, c = lane + 64 * u;
-          double val = (r == c) ? 1.0 : 0.0;
-          if (u < ncu && r < n && c < n) val = Ain[(size_t)r * n + c];
-          v_[rr][u] = val;
-        }
-      }
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int r = r0 + 4 * rr, c = lane + 64 * u;
-          if (u < ncu && r < np && c < np) M[(size_t)r * ld + c] = v_[rr][u];
-        }
-      }
-    }
-    for (int r = t; r < np; r += 256) {
-      M[(size_t)r * ld + np] = (r < n && !trans) ? b[r] : 0.0;
-      sh.rmap[r] = r;
-    }
-  }
-  if (t == 0) sh.sing = 0;
-  __syncthreads();
-
+  // Wave 0 factors the first panel straight from the input while waves 1-3
+  // load the other columns of [A | b] (padded with an identity block): wave w
+  // takes rows w - 1, w + 2, ..., lane l columns 16 + l, 80 + l, ...; sixteen
+  // rows per batch.
+  //
   // Panel k+1 is factored while panel k's update of the other columns runs
   // (one panel of lookahead).  Per panel: U12 of the next panel's columns
   // (and of one more block per other wave), the next panel's tile column
@@ -1071,8 +1055,10 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   // map only after the barrier, once nobody reads the old one.
   int lpos[MR], phys[MR];
   if (wave == 0) {
+    for (int r = lane; r < np; r += 64) sh.rmap[r] = r;
+    if (lane == 0) sh.sing = 0;
     int sg;
-    lu_factor_panel<MR>(M, ld, np, rmap, 0, lane, sh, lpos, phys, sg);
+    lu_factor_panel<MR, true>(M, ld, np, rmap, 0, lane, sh, lpos, phys, sg, Ain, n);
     if (sg && lane == 0) sh.sing = 1;
     if (!sg) {
       wave_memory_sync();
@@ -1080,6 +1066,30 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       for (int m = 0; m < MR; ++m)
         if (lpos[m] >= 0) sh.rmap[lpos[m]] = phys[m];
     }
+  } else {
+    const int ncu = (np - LU_NB + 63) / 64;  // column chunks of 64 right of the panel (<= 4)
+    for (int r0 = wave - 1; r0 < np; r0 += 3 * 16) {
+      double v_[16][4];
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + 3 * rr, c = LU_NB + lane + 64 * u;
+          double val = (r == c) ? 1.0 : 0.0;
+          if (u < ncu && r < n && c < n) val = Ain[(size_t)r * n + c];
+          v_[rr][u] = val;
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + 3 * rr, c = LU_NB + lane + 64 * u;
+          if (u < ncu && r < np && c < np) M[(size_t)r * ld + c] = v_[rr][u];
+        }
+      }
+    }
+    for (int r = t - 64; r < np; r += 192) M[(size_t)r * ld + np] = (r < n && !trans) ? b[r] : 0.0;
   }
   __syncthreads();
   for (int k0 = 0; k0 < np && !sh.sing; k0 += LU_NB) {
@@ -1111,7 +1121,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
     __syncthreads();
     if (wave == 0) {
       int sg;
-      lu_factor_panel<MR>(M, ld, np, rmap, j0, lane, sh, lpos, phys, sg);
+      lu_factor_panel<MR, false>(M, ld, np, rmap, j0, lane, sh, lpos, phys, sg);
       if (sg && lane == 0) sh.sing = 1;
     } else {
       // a block's U12 rows, written by lanes 0-15, are read by every lane of
@@ -1255,7 +1265,10 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     const int r = lane + 64 * m;
-    if (r < n) x[r] = w[m];
+    if (r < n) {
+      x[r] = w[m];
+      if (cout) cout[r] = fma(-rho, w[m], cin[r]);
+    }
   }
   if (lane == 0) flag[0] = 0;
 }
@@ -1266,9 +1279,9 @@ constexpr int kLUStaticBytes = (int)sizeof(LUShared) + 256;
 template <bool IN_LDS, int MR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void lu_solve_kernel(
     int n, const double* __restrict__ Ain, const double* __restrict__ b, double* x, double* __restrict__ Aglob,
-    int* piv, int trans, int* flag) {
+    int* piv, int trans, int* flag, const double* __restrict__ cin, double rho, double* __restrict__ cout) {
   extern __shared__ double lds[];
-  lu_body<IN_LDS, MR>(n, Ain, b, x, Aglob, piv, trans, flag, lds);
+  lu_body<IN_LDS, MR>(n, Ain, b, x, Aglob, piv, trans, flag, lds, cin, rho, cout);
 }
 
 // --------------------------------------------------------------------------
@@ -1604,7 +1617,7 @@ void lu_setup() {
 }
 
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x, int trans,
-                           hipStream_t st) {
+                           hipStream_t st, const double* cin, double rho, double* cout) {
   const int n = v.n;
   const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
   // factors of [A | b], padded, in dynamic LDS when they fit
@@ -1616,17 +1629,17 @@ hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, dou
   if (np <= 128) {
     if (fits)
       hipLaunchKernelGGL((lu_solve_kernel<true, 2>), dim3(1), dim3(256), lds_bytes, st, n, A, b, x, v.LU, v.piv,
-                         trans, v.flag);
+                         trans, v.flag, cin, rho, cout);
     else
       hipLaunchKernelGGL((lu_solve_kernel<false, 2>), dim3(1), dim3(256), 0, st, n, A, b, x, v.LU, v.piv, trans,
-                         v.flag);
+                         v.flag, cin, rho, cout);
   } else {
     if (fits)
       hipLaunchKernelGGL((lu_solve_kernel<true, 4>), dim3(1), dim3(256), lds_bytes, st, n, A, b, x, v.LU, v.piv,
-                         trans, v.flag);
+                         trans, v.flag, cin, rho, cout);
     else
       hipLaunchKernelGGL((lu_solve_kernel<false, 4>), dim3(1), dim3(256), 0, st, n, A, b, x, v.LU, v.piv, trans,
-                         v.flag);
+                         v.flag, cin, rho, cout);
   }
   return hipGetLastError();
 }
