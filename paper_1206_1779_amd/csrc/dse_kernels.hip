@@ -207,7 +207,7 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
 
   const int t = threadIdx.x;
   const int lane = t & 63;
-  const int wave = t >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: angle data through scalar loads
   const int KS = v.KS;
   const int ntile = v.nqt * KS;                   // partial tiles per row; tile = qt * KS + ks
   const int qt = tile / KS, ks = tile - qt * KS;
@@ -825,14 +825,30 @@ struct LUShared {
   int sing;
 };
 
-// One panel column.  The panel's registers shift left by four after every
-// group of four columns, so with group offset G (compile time) register cc
-// holds column k0 + G + cc for cc < LU_NB - G, and P[m][O] is column
-// kc = k0 + G + O.  lpos[m] is the logical position of register row m.
-template <int MR, int O, int G>
-__device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], LUShared& sh, int lane,
-                                       int kc, int& sing) {
-  constexpr int CE = LU_NB - G;  // registers holding columns of this panel
+// The panel's columns run as a pipeline.  Column O has three stages:
+//   A(O)  pivot: wave maximum of |P[.][O]| over the rows not yet used, the
+//         first register row holding it, its reciprocal;
+//   B(O)  interchange (logical positions only), multipliers of column O and
+//         the update of column O + 1;
+//   C(O)  the update of columns O + 2 .. 15.
+// Order: A(O), C(O - 1), B(O).  A(O) needs column O only (final after B(O-1)
+// and C(O-2)), so its DPP reduction and C(O - 1)'s lane reads and FMAs are
+// independent and interleave; the serial chain per column is A and B.  Every
+// element receives the same FMAs in the same order as in a column-by-column
+// elimination.  The code is branch-free: a singular column only raises sing
+// (the caller then abandons the factorisation).  lpos[m] is the logical
+// position of register row m (-1: no row); lane O of the wave collects
+// column O's interchange and reciprocal pivot.
+struct LUPivot {
+  int lp;      // lane holding the pivot row
+  int mp;      // its register row
+  int p;       // its logical position
+  double inv;  // 1 / pivot
+};
+
+template <int MR, int O>
+__device__ __forceinline__ LUPivot lu_pivot(const double (&P)[MR][LU_NB], const int (&lpos)[MR], int kc,
+                                            int& sing) {
   double cand[MR];
   double lmax = -1.0;
 #pragma unroll
@@ -841,81 +857,81 @@ __device__ __forceinline__ void lu_col(double (&P)[MR][LU_NB], int (&lpos)[MR], 
     lmax = fmax(lmax, cand[m]);
   }
   const double gmax = wave_max_nonneg(lmax);
-  if (!(gmax > 0.0) || isinf(gmax)) { sing = 1; return; }
-  // first register row (m, then lane) holding the maximum
+  sing |= (!(gmax > 0.0) || isinf(gmax)) ? 1 : 0;
   int lp = -1, mp = 0;
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     const unsigned long long mk = __ballot(cand[m] == gmax);
     if (lp < 0 && mk) { lp = (int)__builtin_ctzll(mk); mp = m; }
   }
+  lp &= 63;  // no maximum only when singular: any lane
   int lsel = lpos[0];
   double psel = P[0][O];
 #pragma unroll
   for (int m = 1; m < MR; ++m)
     if (mp == m) { lsel = lpos[m]; psel = P[m][O]; }
-  const int p = __builtin_amdgcn_readlane(lsel, lp);
-  const double inv = 1.0 / readlane_d(psel, lp);
-  // the pivot row's remaining entries (CE - O - 1 of them, 7.5 on average over
-  // a panel), read across lanes from the lane that holds it
-  double rp[CE];
+  LUPivot r;
+  r.lp = lp;
+  r.mp = mp;
+  r.p = __builtin_amdgcn_readlane(lsel, lp);
+  r.inv = 1.0 / readlane_d(psel, lp);
+  return r;
+}
+
+// Entry cc of the pivot row, read across lanes from the lane that holds it
+// (cc is a constant once the callers' loops are unrolled).
+template <int MR>
+__device__ __forceinline__ double lu_prow(const double (&P)[MR][LU_NB], const LUPivot& pv, int cc) {
+  double sel = P[0][cc];
 #pragma unroll
-  for (int cc = O + 1; cc < CE; ++cc) {
-    double sel = P[0][cc];
+  for (int m = 1; m < MR; ++m) if (pv.mp == m) sel = P[m][cc];
+  return readlane_d(sel, pv.lp);
+}
+
+template <int MR, int O>
+__device__ __forceinline__ void lu_stage_b(double (&P)[MR][LU_NB], int (&lpos)[MR], const LUPivot& pv, int kc,
+                                           int lane, int& mypiv, double& myinv) {
+  mypiv = lane == O ? pv.p : mypiv;
+  myinv = lane == O ? pv.inv : myinv;
 #pragma unroll
-    for (int m = 1; m < MR; ++m) if (mp == m) sel = P[m][cc];
-    rp[cc] = readlane_d(sel, lp);
+  for (int m = 0; m < MR; ++m) {
+    const int q = lpos[m];
+    lpos[m] = q == kc ? pv.p : (q == pv.p ? kc : q);
   }
-  if (lane == 0) {
-    sh.spiv[kc] = p;
-    sh.dinv[kc] = inv;
-  }
-  if (p != kc) {
-#pragma unroll
-    for (int m = 0; m < MR; ++m) {
-      if (lpos[m] == kc) lpos[m] = p;
-      else if (lpos[m] == p) lpos[m] = kc;
-    }
-  }
+  double r1 = 0.0;
+  if constexpr (O + 1 < LU_NB) r1 = lu_prow<MR>(P, pv, O + 1);
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     const bool below = lpos[m] > kc;
-    const double l = below ? P[m][O] * inv : 0.0;
+    const double l = below ? P[m][O] * pv.inv : 0.0;
     if (below) P[m][O] = l;
-#pragma unroll
-    for (int cc = O + 1; cc < CE; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
+    if constexpr (O + 1 < LU_NB) P[m][O + 1] = fma(-l, r1, P[m][O + 1]);
   }
 }
 
-// Columns G .. LU_NB - 1 of the panel, four at a time; each group's four
-// finished columns go back to the physical rows before the shift.
-template <int MR, int G>
-__device__ __forceinline__ void lu_panel(double (&P)[MR][LU_NB], int (&lpos)[MR], const int (&phys)[MR], double* M,
-                                         int ld, int lane, int k0, LUShared& sh, int& sg) {
-  lu_col<MR, 0, G>(P, lpos, sh, lane, k0 + G + 0, sg);
-  if (sg) return;
-  lu_col<MR, 1, G>(P, lpos, sh, lane, k0 + G + 1, sg);
-  if (sg) return;
-  lu_col<MR, 2, G>(P, lpos, sh, lane, k0 + G + 2, sg);
-  if (sg) return;
-  lu_col<MR, 3, G>(P, lpos, sh, lane, k0 + G + 3, sg);
-  if (sg) return;
+template <int MR, int O>
+__device__ __forceinline__ void lu_stage_c(double (&P)[MR][LU_NB], const int (&lpos)[MR], const LUPivot& pv,
+                                           int kc) {
+  if constexpr (O + 2 < LU_NB) {
+    double rp[LU_NB];
 #pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    if (lpos[m] >= 0) {
-      double* Mr = M + (size_t)phys[m] * ld + k0 + G;
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) Mr[cc] = P[m][cc];
-    }
-  }
-  if constexpr (G + 4 < LU_NB) {
+    for (int cc = O + 2; cc < LU_NB; ++cc) rp[cc] = lu_prow<MR>(P, pv, cc);
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
+      const double l = lpos[m] > kc ? P[m][O] : 0.0;  // the multiplier B(O) stored
 #pragma unroll
-      for (int cc = 0; cc < LU_NB - G - 4; ++cc) P[m][cc] = P[m][cc + 4];
+      for (int cc = O + 2; cc < LU_NB; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
     }
-    lu_panel<MR, G + 4>(P, lpos, phys, M, ld, lane, k0, sh, sg);
   }
+}
+
+template <int MR, int O>
+__device__ __forceinline__ void lu_pipe(double (&P)[MR][LU_NB], int (&lpos)[MR], int k0, int lane, int& sing,
+                                        int& mypiv, double& myinv, const LUPivot& prev) {
+  const LUPivot pv = lu_pivot<MR, O>(P, lpos, k0 + O, sing);
+  if constexpr (O > 0) lu_stage_c<MR, O - 1>(P, lpos, prev, k0 + O - 1);
+  lu_stage_b<MR, O>(P, lpos, pv, k0 + O, lane, mypiv, myinv);
+  if constexpr (O + 1 < LU_NB) lu_pipe<MR, O + 1>(P, lpos, k0, lane, sing, mypiv, myinv, pv);
 }
 
 // Loads the rows of the panel at k0 (positions k0 ..) into wave 0's registers
@@ -944,7 +960,24 @@ __device__ __forceinline__ void lu_factor_panel(double* M, int ld, int np, const
     }
   }
   sg = 0;
-  lu_panel<MR, 0>(P, lpos, phys, M, ld, lane, k0, sh, sg);
+  int mypiv = 0;
+  double myinv = 0.0;
+  const LUPivot none{0, 0, 0, 0.0};
+  lu_pipe<MR, 0>(P, lpos, k0, lane, sg, mypiv, myinv, none);
+  // the factored panel back to its physical rows; interchanges and
+  // reciprocal pivots from lanes 0 .. 15
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    if (lpos[m] >= 0) {
+      double* Mr = M + (size_t)phys[m] * ld + k0;
+#pragma unroll
+      for (int cc = 0; cc < LU_NB; ++cc) Mr[cc] = P[m][cc];
+    }
+  }
+  if (lane < LU_NB) {
+    sh.spiv[k0 + lane] = mypiv;
+    sh.dinv[k0 + lane] = myinv;
+  }
 }
 
 // U12 = L11^{-1} A12 for the columns [jc, jc + ncols) (ncols <= 16): lanes
