@@ -228,11 +228,15 @@ __device__ __forceinline__ void slice_reduce(T* vals, int lane, int& base, bool&
 enum { MODE_RES = 0, MODE_JAC = 1, MODE_VJP = 2, MODE_VTH = 3 };
 
 // LDS of one point-kernel block (doubles): red[3][4] at 0, bs[2][4][64] at 16,
-// ds[4][NT*NJ] at 528; with CLDS the coefficients a | b at 528 + 8 NJ.
-template <int NJ, bool CLDS>
-__host__ __device__ constexpr int point_smem() { return 528 + (CLDS ? 10 : 8) * NJ; }
+// ds[4][NT*NJ] at 528; in the batch kernel the coefficients a | b at 528 + 8 NJ.
+template <int NJ, bool BATCH>
+__host__ __device__ constexpr int point_smem() { return 528 + (BATCH ? 10 : 8) * NJ; }
 
-template <int KIND, int NJ, int MODE, bool MIX = false, bool CLDS = false>
+// BATCH: a body of the batch kernel, which holds one body per order and row
+// kind and so has few registers to spare: the coefficients are staged in LDS
+// and ln z comes from the library's log (the series below needs more
+// registers and cost the batch kernel half its occupancy).
+template <int KIND, int NJ, int MODE, bool MIX = false, bool BATCH = false>
 __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int row, int tile,
                                            double* __restrict__ smem) {
   using TL = Tile<KIND, NJ>;
@@ -282,11 +286,11 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   // Chebyshev coefficients a | b: wave-uniform, read a chunk at a time inside
   // the recurrence; the chunk loop stays a loop, so they are neither held in
   // registers across it nor gathered at its top.  Read through the scalar
-  // cache into scalar registers (no LDS traffic), or, with CLDS (the batch
-  // kernel, whose many bodies leave no scalar registers to spare), staged in
-  // LDS and read with broadcast loads.
+  // cache into scalar registers (no LDS traffic), or, in the batch kernel
+  // (no scalar registers to spare), staged in LDS and read with broadcast
+  // loads.
   const double* __restrict__ coef = v.coef;
-  if constexpr (CLDS) {
+  if constexpr (BATCH) {
     double* __restrict__ cl = smem + 528 + 8 * NJ;
     for (int j = t; j < 2 * NJ; j += 256) cl[j] = v.coef[j];
     __syncthreads();
@@ -312,7 +316,7 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     const double st2 = ang[4 * Kp + k];
 
     const double w = fma(Bw, s2h, Aw);
-    const double lz = lnmx + log_series(w);
+    const double lz = lnmx + (BATCH ? log(w) : log_series(w));
     double s = (lz - ph.L0) * ph.invL1;
     s = fmin(fmax(s, -1.0), 1.0);
     const double s2 = s + s;
@@ -367,7 +371,7 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     } else if (lz > ph.ln_lam2) {
       const double l = lz - ph.ln_lam2;
       const double arg = fma(ph.omega, l, 1.0);
-      const double L = log_series(arg);
+      const double L = BATCH ? log(arg) : log_series(arg);
       XZ = ph.gamma * L;
       XG = ph.delta * L;
       if (WEIGHTED) dXa = ph.omega_per_alpha * l / arg;
