@@ -169,6 +169,7 @@ def bench_adjoint(dse, workloads, torch) -> dict:
         return float(((B @ rr.c[:nz]) ** 2).sum())
 
     ift()
+    loss(cfg["alpha_mu"], cfg["g0_inv"])  # first use of the loss's own kernels outside the timing
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g = ift()
