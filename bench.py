@@ -191,6 +191,34 @@ def bench_adjoint(dse, workloads, torch) -> dict:
             "dL_dG0": {"ift": dG0, "fd": fd_g, "rel_diff": abs(dG0 - fd_g) / abs(fd_g)}}
 
 
+def bench_fd(dse, workloads, torch) -> dict:
+    """N = 64: the Newton matrix by the paper's own method, central differences
+    of the residual (2n full residual evaluations, dse_jacobian_fd), against
+    the analytic matrix of the same context, both on this GPU; the ratio
+    separates the gain of the analytic derivatives from that of the hardware."""
+    import numpy as np
+    cfg = workloads.config("cfg2")
+    s = dse.Solver(**cfg)
+    c = s.start_guess()
+    s.jacobian_fd(c)  # warm-up
+    s.jacobian(c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Jfd = s.jacobian_fd(c)
+    torch.cuda.synchronize()
+    t_fd = time.perf_counter() - t0
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        J, _ = s.jacobian(c)
+    torch.cuda.synchronize()
+    t_an = (time.perf_counter() - t0) / reps
+    J, Jfd = J.cpu().numpy(), Jfd.cpu().numpy()
+    return {"fd_ms": t_fd * 1e3, "analytic_ms": t_an * 1e3, "speedup": t_fd / t_an,
+            "residual_evaluations": 2 * s.n,
+            "normwise_rel_diff": float(np.linalg.norm(J - Jfd) / np.linalg.norm(J))}
+
+
 def bench_mixed(dse, workloads, torch) -> dict:
     """N = 128 per function, 1024+256 radial x 128 angular: the Newton matrix
     with FP32 derivative sums and FP32 MFMA contraction against FP64 (device
@@ -240,7 +268,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--solves", type=int, default=5, help="Newton solves timed for s/solve")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint comparisons")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, mixed and finite-difference comparisons")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device five times (reference for HBM counters)")
     args = ap.parse_args()
@@ -346,6 +374,7 @@ def main() -> int:
         out["batched"] = bench_batched(dse, workloads, torch)
         out["adjoint"] = bench_adjoint(dse, workloads, torch)
         out["mixed"] = bench_mixed(dse, workloads, torch)
+        out["fd_jacobian"] = bench_fd(dse, workloads, torch)
     if not args.no_cpu:
         cb = cpu_baseline(cfg, c.cpu().numpy())
         cb["gpu_speedup"] = value / cb["value"]

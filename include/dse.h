@@ -156,6 +156,16 @@ dse_status dse_residual(dse_ctx* ctx, const double* d_c, double* d_F, double* d_
  * integrands) and, if d_F != NULL, F at the same c. */
 dse_status dse_jacobian(dse_ctx* ctx, const double* d_c, double* d_J, double* d_F);
 
+/* Newton matrix by central differences of the residual, the paper's own
+ * method (Sec. 4.2, finite-difference Jacobian with a step relative to each
+ * coefficient): column j = (F(c + h_j e_j) - F(c - h_j e_j)) / (2 h_j) with
+ * h_j = h_rel max(1, |c_j|).  2n full residual evaluations, enqueued on the
+ * context's stream; for comparison with dse_jacobian (same layout: d_J is
+ * [n][n] row-major on the device, d_c [n] on the device).  h_rel in (0, 1),
+ * else DSE_E_INVALID.  Uses the context's scratch vectors, so it must not
+ * overlap other calls on the same context. */
+dse_status dse_jacobian_fd(dse_ctx* ctx, const double* d_c, double* d_J, double h_rel);
+
 /* Solves F(c) = 0 by the under-relaxed Newton iteration of Sec. 3 starting
  * from d_c (overwritten by the last iterate).  opts may be NULL (tol 1e-10,
  * max_iter 60, extra_iters 0, max_halvings 30, step_tol 1e-14); h_report

@@ -602,6 +602,24 @@ dse_status dse_jacobian(dse_ctx* ctx, const double* d_c, double* d_J, double* d_
   return eval_jacobian(ctx, d_c, d_J, d_F, d_F ? ctx->v.St : nullptr);
 }
 
+dse_status dse_jacobian_fd(dse_ctx* ctx, const double* d_c, double* d_J, double h_rel) {
+  if (!ctx) return DSE_E_INVALID;
+  if (!d_c || !d_J) { set_err(ctx->err, "d_c and d_J must not be NULL"); return DSE_E_INVALID; }
+  if (!(h_rel > 0.0) || !(h_rel < 1.0)) { set_err(ctx->err, "h_rel must lie in (0, 1)"); return DSE_E_INVALID; }
+  DeviceGuard dg(ctx->device);
+  const dse::Views& v = ctx->v;
+  double* hbuf = v.scal + 4;
+  for (int j = 0; j < v.n; ++j) {
+    HIP_TRY(ctx, dse::launch_fd_shift(v.n, d_c, j, h_rel, 1.0, v.ct, hbuf, ctx->st));
+    dse_status s = eval_residual(ctx, v.ct, v.Ft, v.St);
+    if (s != DSE_OK) return s;
+    HIP_TRY(ctx, dse::launch_fd_shift(v.n, d_c, j, h_rel, -1.0, v.ct, hbuf, ctx->st));
+    if ((s = eval_residual(ctx, v.ct, v.F, v.S)) != DSE_OK) return s;
+    HIP_TRY(ctx, dse::launch_fd_column(v.n, v.Ft, v.F, hbuf, j, d_J, ctx->st));
+  }
+  return DSE_OK;
+}
+
 dse_status dse_set_timing(dse_ctx* ctx, int32_t on) {
   if (!ctx) return DSE_E_INVALID;
   DeviceGuard dg(ctx->device);

@@ -789,6 +789,25 @@ __global__ __launch_bounds__(256) void norms_kernel(int n, const double* F, cons
   norms_body(n, F, S, d, out);
 }
 
+// Central differences of the residual (the paper's own Jacobian, Sec. 4.2):
+// the shifted coefficients c + sgn h e_j with h = h_rel max(1, |c_j|), h kept
+// in hbuf[0] for the column kernel; then column j of J from the two residuals.
+__global__ void fd_shift_kernel(int n, const double* __restrict__ c, int j, double h_rel, double sgn,
+                                double* __restrict__ cs, double* __restrict__ hbuf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double cj = c[j];
+  const double h = h_rel * fmax(1.0, fabs(cj));
+  cs[i] = i == j ? cj + sgn * h : c[i];
+  if (i == 0) hbuf[0] = h;
+}
+
+__global__ void fd_column_kernel(int n, const double* __restrict__ Fp, const double* __restrict__ Fm,
+                                 const double* __restrict__ hbuf, int j, double* __restrict__ J) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) J[(size_t)i * n + j] = (Fp[i] - Fm[i]) / (2.0 * hbuf[0]);
+}
+
 __global__ void axpy_kernel(int n, const double* c, double rho, const double* d, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = fma(-rho, d[i], c[i]);
@@ -1657,6 +1676,18 @@ hipError_t launch_residual_rows(const Views& v, const Phys& ph, double* F, doubl
 hipError_t launch_norms(const Views& v, const double* F, const double* S, const double* d, double* out,
                         hipStream_t st) {
   hipLaunchKernelGGL(norms_kernel, dim3(1), dim3(256), 0, st, v.n, F, S, d, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fd_shift(int n, const double* c, int j, double h_rel, double sgn, double* cs, double* hbuf,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(fd_shift_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, c, j, h_rel, sgn, cs, hbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_fd_column(int n, const double* Fp, const double* Fm, const double* hbuf, int j, double* J,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(fd_column_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Fp, Fm, hbuf, j, J);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "HIP device error", 3: "workspace t
 
 EXPORTS = [
     "dse_params_default", "dse_workspace_bytes", "dse_init", "dse_destroy", "dse_start_guess",
-    "dse_residual", "dse_jacobian", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
+    "dse_residual", "dse_jacobian", "dse_jacobian_fd", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
     "dse_last_error", "dse_sizes", "dse_set_timing", "dse_read_timings", "dse_vjp",
     "dse_set_physics", "dse_newton_step", "dse_set_graphs",
     "dse_batch_workspace_bytes", "dse_batch_init", "dse_batch_destroy", "dse_batch_last_error",
@@ -90,6 +90,7 @@ def load():
             "dse_start_guess": (C.c_int, [vp, vp]),
             "dse_residual": (C.c_int, [vp, vp, vp, vp]),
             "dse_jacobian": (C.c_int, [vp, vp, vp, vp]),
+            "dse_jacobian_fd": (C.c_int, [vp, vp, vp, C.c_double]),
             "dse_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
             "dse_lu_solve": (C.c_int, [vp, vp, vp, vp, C.c_int32]),
             "dse_status_string": (C.c_char_p, [C.c_int]),
@@ -234,6 +235,14 @@ class Solver:
         with torch.cuda.device(self.device):
             self._check(self.lib.dse_jacobian(self.h, _ptr(c), _ptr(J), _ptr(F)))
         return (J, F) if with_F else J
+
+    def jacobian_fd(self, c, h_rel: float = 1e-5) -> torch.Tensor:
+        """Newton matrix by central differences of the residual (dse_jacobian_fd)."""
+        c = self._vec(c)
+        J = torch.empty(self.n, self.n, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_jacobian_fd(self.h, _ptr(c), _ptr(J), float(h_rel)))
+        return J
 
     def lu_solve(self, J, b, trans: bool = False) -> torch.Tensor:
         J = torch.as_tensor(J, dtype=torch.float64).to(self.device).contiguous()
