@@ -219,6 +219,27 @@ def bench_fd(dse, workloads, torch) -> dict:
             "normwise_rel_diff": float(np.linalg.norm(J - Jfd) / np.linalg.norm(J))}
 
 
+def bench_coupling(dse, workloads, torch) -> dict:
+    """N = 64: the running coupling alpha(u) = alpha(mu^2) G^2 Z at 2^17
+    log-spaced momenta from 1e-6 eps2 to 4 lambda2 on the converged solution
+    (G(0) = 15), and its value below eps2, where the IR power laws cancel in
+    G^2 Z and alpha is flat."""
+    cfg = workloads.config("cfg2")
+    s = dse.Solver(**cfg)
+    c = s.newton().c
+    m = 1 << 17
+    u = torch.logspace(math.log10(cfg["eps2"]) - 6, math.log10(4 * cfg["lambda2"]), m,
+                       dtype=torch.float64, device=c.device)
+    s.running_coupling(c, u)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    al, _, _ = s.running_coupling(c, u)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return {"points": m, "ms": t * 1e3, "points_per_s": m / t, "alpha_ir": float(al[0]),
+            "g0_inv": cfg["g0_inv"]}
+
+
 def bench_mixed(dse, workloads, torch) -> dict:
     """N = 128 per function, 1024+256 radial x 128 angular: the Newton matrix
     with FP32 derivative sums and FP32 MFMA contraction against FP64 (device
@@ -375,6 +396,7 @@ def main() -> int:
         out["adjoint"] = bench_adjoint(dse, workloads, torch)
         out["mixed"] = bench_mixed(dse, workloads, torch)
         out["fd_jacobian"] = bench_fd(dse, workloads, torch)
+        out["coupling"] = bench_coupling(dse, workloads, torch)
     if not args.no_cpu:
         cb = cpu_baseline(cfg, c.cpu().numpy())
         cb["gpu_speedup"] = value / cb["value"]

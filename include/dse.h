@@ -166,6 +166,16 @@ dse_status dse_jacobian(dse_ctx* ctx, const double* d_c, double* d_J, double* d_
  * overlap other calls on the same context. */
 dse_status dse_jacobian_fd(dse_ctx* ctx, const double* d_c, double* d_J, double h_rel);
 
+/* The dressings and the running coupling at m arbitrary momenta u > 0
+ * (Sec. 2 running coupling alpha(x) = alpha(mu^2) G^2(x) Z(x); Sec. 3
+ * expansion with the IR power laws below eps2 and the UV logarithms above
+ * lambda2, the same extension the equations use): d_alpha[i] = alpha(u_i),
+ * d_lnZ[i] = ln Z(u_i), d_lnG[i] = ln G(u_i).  d_c [n], d_u [m] and the
+ * outputs (each nullable) on the device; enqueued on the context's stream.
+ * m < 0 or a NULL d_c / d_u with m > 0: DSE_E_INVALID. */
+dse_status dse_running_coupling(dse_ctx* ctx, const double* d_c, const double* d_u, int32_t m, double* d_alpha,
+                                double* d_lnZ, double* d_lnG);
+
 /* Solves F(c) = 0 by the under-relaxed Newton iteration of Sec. 3 starting
  * from d_c (overwritten by the last iterate).  opts may be NULL (tol 1e-10,
  * max_iter 60, extra_iters 0, max_halvings 30, step_tol 1e-14); h_report

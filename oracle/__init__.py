@@ -12,6 +12,7 @@ every wrapper only marshals numpy arrays.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -169,6 +170,13 @@ def lnZ(p: Params, a, u: float) -> float:
 def lnG(p: Params, b, u: float) -> float:
     b, pb = _arr(b)
     return load().dse_ref_lnG(C.byref(p), pb, float(u))
+
+
+def running_coupling(p: Params, c, u: float) -> float:
+    """alpha(u) = alpha(mu^2) G(u)^2 Z(u) (Sec. 2 running coupling), from the
+    dressings lnG, lnZ above (series plus IR / UV extension)."""
+    c = np.asarray(c, dtype=np.float64)
+    return p.alpha_mu * math.exp(2.0 * lnG(p, c[p.n_z:], u) + lnZ(p, c[:p.n_z], u))
 
 
 def kernel_Q(x, y, theta):

@@ -602,6 +602,18 @@ dse_status dse_jacobian(dse_ctx* ctx, const double* d_c, double* d_J, double* d_
   return eval_jacobian(ctx, d_c, d_J, d_F, d_F ? ctx->v.St : nullptr);
 }
 
+dse_status dse_running_coupling(dse_ctx* ctx, const double* d_c, const double* d_u, int32_t m, double* d_alpha,
+                                double* d_lnZ, double* d_lnG) {
+  if (!ctx) return DSE_E_INVALID;
+  if (m < 0 || (m > 0 && (!d_c || !d_u))) {
+    set_err(ctx->err, "m must be >= 0, d_c and d_u non-NULL");
+    return DSE_E_INVALID;
+  }
+  DeviceGuard dg(ctx->device);
+  HIP_TRY(ctx, dse::launch_coupling(ctx->v, ctx->ph, ctx->p.alpha_mu, d_c, d_u, m, d_alpha, d_lnZ, d_lnG, ctx->st));
+  return DSE_OK;
+}
+
 dse_status dse_jacobian_fd(dse_ctx* ctx, const double* d_c, double* d_J, double h_rel) {
   if (!ctx) return DSE_E_INVALID;
   if (!d_c || !d_J) { set_err(ctx->err, "d_c and d_J must not be NULL"); return DSE_E_INVALID; }

@@ -789,6 +789,43 @@ __global__ __launch_bounds__(256) void norms_kernel(int n, const double* F, cons
   norms_body(n, F, S, d, out);
 }
 
+// The dressings and the running coupling at arbitrary momenta u (Sec. 2):
+// ln Z(u), ln G(u) from the Chebyshev series (Sec. 3, c_0/2 convention) plus
+// the IR power laws below eps2 and the UV logarithms above lambda2, and
+// alpha(u) = alpha(mu^2) G(u)^2 Z(u).  One thread per point; outputs nullable.
+__global__ __launch_bounds__(256) void coupling_kernel(Views v, Phys ph, double alpha_mu,
+                                                       const double* __restrict__ c,
+                                                       const double* __restrict__ u, int m,
+                                                       double* __restrict__ alpha, double* __restrict__ lnZo,
+                                                       double* __restrict__ lnGo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double lu = log(u[i]);
+  const double s = fmin(fmax((lu - ph.L0) * ph.invL1, -1.0), 1.0);
+  const double s2 = s + s;
+  double z = 0.5 * c[0], g = 0.5 * c[v.n_z];
+  double Tp = 1.0, Tc = s;
+  const int nmax = v.n_z > v.n_g ? v.n_z : v.n_g;
+  for (int j = 1; j < nmax; ++j) {
+    if (j < v.n_z) z = fma(c[j], Tc, z);
+    if (j < v.n_g) g = fma(c[v.n_z + j], Tc, g);
+    const double Tn = fma(s2, Tc, -Tp);
+    Tp = Tc;
+    Tc = Tn;
+  }
+  if (lu < ph.ln_eps2) {
+    z += 2.0 * ph.kappa * (lu - ph.ln_eps2);
+    g += -ph.kappa * (lu - ph.ln_eps2);
+  } else if (lu > ph.ln_lam2) {
+    const double L = log(fma(ph.omega, lu - ph.ln_lam2, 1.0));
+    z += ph.gamma * L;
+    g += ph.delta * L;
+  }
+  if (alpha) alpha[i] = alpha_mu * exp(2.0 * g + z);
+  if (lnZo) lnZo[i] = z;
+  if (lnGo) lnGo[i] = g;
+}
+
 // Central differences of the residual (the paper's own Jacobian, Sec. 4.2):
 // the shifted coefficients c + sgn h e_j with h = h_rel max(1, |c_j|), h kept
 // in hbuf[0] for the column kernel; then column j of J from the two residuals.
@@ -1676,6 +1713,14 @@ hipError_t launch_residual_rows(const Views& v, const Phys& ph, double* F, doubl
 hipError_t launch_norms(const Views& v, const double* F, const double* S, const double* d, double* out,
                         hipStream_t st) {
   hipLaunchKernelGGL(norms_kernel, dim3(1), dim3(256), 0, st, v.n, F, S, d, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_coupling(const Views& v, const Phys& ph, double alpha_mu, const double* c, const double* u, int m,
+                           double* alpha, double* lnZ, double* lnG, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(coupling_kernel, dim3((m + 255) / 256), dim3(256), 0, st, v, ph, alpha_mu, c, u, m, alpha, lnZ,
+                     lnG);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "HIP device error", 3: "workspace t
 
 EXPORTS = [
     "dse_params_default", "dse_workspace_bytes", "dse_init", "dse_destroy", "dse_start_guess",
-    "dse_residual", "dse_jacobian", "dse_jacobian_fd", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
+    "dse_residual", "dse_jacobian", "dse_jacobian_fd", "dse_running_coupling", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
     "dse_last_error", "dse_sizes", "dse_set_timing", "dse_read_timings", "dse_vjp",
     "dse_set_physics", "dse_newton_step", "dse_set_graphs",
     "dse_batch_workspace_bytes", "dse_batch_init", "dse_batch_destroy", "dse_batch_last_error",
@@ -91,6 +91,7 @@ def load():
             "dse_residual": (C.c_int, [vp, vp, vp, vp]),
             "dse_jacobian": (C.c_int, [vp, vp, vp, vp]),
             "dse_jacobian_fd": (C.c_int, [vp, vp, vp, C.c_double]),
+            "dse_running_coupling": (C.c_int, [vp, vp, vp, C.c_int32, vp, vp, vp]),
             "dse_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
             "dse_lu_solve": (C.c_int, [vp, vp, vp, vp, C.c_int32]),
             "dse_status_string": (C.c_char_p, [C.c_int]),
@@ -243,6 +244,16 @@ class Solver:
         with torch.cuda.device(self.device):
             self._check(self.lib.dse_jacobian_fd(self.h, _ptr(c), _ptr(J), float(h_rel)))
         return J
+
+    def running_coupling(self, c, u):
+        """alpha(u), ln Z(u), ln G(u) at the momenta u (dse_running_coupling)."""
+        c = self._vec(c)
+        u = torch.as_tensor(u, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+        out = [torch.empty_like(u) for _ in range(3)]
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_running_coupling(self.h, _ptr(c), _ptr(u), int(u.numel()),
+                                                       _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))
+        return tuple(out)
 
     def lu_solve(self, J, b, trans: bool = False) -> torch.Tensor:
         J = torch.as_tensor(J, dtype=torch.float64).to(self.device).contiguous()

@@ -318,6 +318,32 @@ def test_ir_exponent_and_fixed_point_from_kernels(ref):
 # --------------------------------------------------------------------------- #
 # derivatives
 
+def test_running_coupling_ir_fixed_point(ref):
+    """Scaling solution (G(0)^-1 = 0), N = 24: alpha(u) = alpha(mu^2) G^2 Z
+    is flat below eps2, where the IR power laws Z ~ u^(2 kappa) and
+    G ~ u^(-kappa) cancel in G^2 Z (Sec. 2), and its value there is the IR
+    fixed point: the paper prints N_c alpha(0) = 8.915 (Sec. 2), the closed
+    form of the IR analysis with kappa = 0.595353 gives
+    (2 pi / 3) Gamma(3 - 2k) Gamma(3 + k) Gamma(1 + k) / (Gamma(2 - k)^2 Gamma(2k))
+    = 8.91512.  The converged discretisation approaches it as N grows
+    (2.6e-3 relative at N = 16, 2.4e-4 at N = 24)."""
+    cfg = workloads.config("cfg1", n_z=24, n_g=24)
+    p = ref.params(**cfg)
+    assert p.g0_inv == 0.0
+    c, r = ref.newton(p, extra_iters=2)
+    assert r["status"] == 0
+    k = p.kappa
+    closed = (2 * math.pi / 3) * math.gamma(3 - 2 * k) * math.gamma(3 + k) * math.gamma(1 + k) / \
+        (math.gamma(2 - k) ** 2 * math.gamma(2 * k))
+    assert abs(closed - 8.915) < 5e-4  # the closed form is the paper's printed number
+    a0 = ref.running_coupling(p, c, p.eps2 * 1e-12)
+    assert abs(p.n_c * a0 / closed - 1.0) < 5e-4
+    for u in (p.eps2, p.eps2 * 1e-3, p.eps2 * 1e-8):
+        assert abs(ref.running_coupling(p, c, u) / a0 - 1.0) < 1e-13
+    # above eps2 the coupling leaves the fixed point and falls towards the UV
+    assert ref.running_coupling(p, c, 1.0) < a0 and ref.running_coupling(p, c, p.lambda2) < ref.running_coupling(p, c, 1.0)
+
+
 def test_analytic_jacobian_matches_central_differences(ref):
     p = ref.params(**workloads.config("cfg1", n_z=10, n_g=12))
     c = ref.start_guess(p) + workloads.perturbation(10, 12, 0.05, seed=1)
