@@ -1198,13 +1198,16 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
         if (lpos[m] >= 0) sh.rmap[lpos[m]] = phys[m];
     }
   } else {
-    const int ncu = (np - LU_NB + 63) / 64;  // column chunks of 64 right of the panel (<= 4)
-    for (int r0 = wave - 1; r0 < np; r0 += 3 * 16) {
-      double v_[16][4];
+    // MR column chunks of 64 right of the panel cover np - 16 < 64 MR columns;
+    // RB rows per batch keep 64 values in flight per lane
+    constexpr int CU = MR, RB = 64 / MR;
+    const int ncu = (np - LU_NB + 63) / 64;
+    for (int r0 = wave - 1; r0 < np; r0 += 3 * RB) {
+      double v_[RB][CU];
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
+      for (int rr = 0; rr < RB; ++rr) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < CU; ++u) {
           const int r = r0 + 3 * rr, c = LU_NB + lane + 64 * u;
           double val = (r == c) ? 1.0 : 0.0;
           if (u < ncu && r < n && c < n) val = Ain[(size_t)r * n + c];
@@ -1212,9 +1215,9 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
         }
       }
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
+      for (int rr = 0; rr < RB; ++rr) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < CU; ++u) {
           const int r = r0 + 3 * rr, c = LU_NB + lane + 64 * u;
           if (u < ncu && r < np && c < np) M[(size_t)r * ld + c] = v_[rr][u];
         }
