@@ -1097,6 +1097,42 @@ __device__ __forceinline__ void lu_u12_block(double* M, int ld, int k0, const in
   for (int c = 1; c < LU_NB; ++c) M[(size_t)pr[c] * ld + j] = u[c];
 }
 
+// The same for a full 16-column block with the whole wave: quad q (lanes
+// 4q .. 4q+3) takes column jc + q, lane g of the quad rows g, g+4, g+8, g+12.
+// Step cc broadcasts u[cc] from its lane inside the quad (DPP quad
+// permutation) and the lanes below subtract L11[c][cc] u[cc]; every element
+// receives the same FMAs in the same order as in the one-lane-per-column form.
+__device__ __forceinline__ double quad_bcast(double v, int o) {
+  switch (o) {
+    case 0: return dpp_d<0x00, 0xf>(v);  // quad_perm [0,0,0,0]
+    case 1: return dpp_d<0x55, 0xf>(v);  // [1,1,1,1]
+    case 2: return dpp_d<0xAA, 0xf>(v);  // [2,2,2,2]
+    default: return dpp_d<0xFF, 0xf>(v);  // [3,3,3,3]
+  }
+}
+
+__device__ __forceinline__ void lu_u12_block16(double* M, int ld, int k0, const int* rmap, int jc, int lane) {
+  const int g = lane & 3;
+  const int j = jc + (lane >> 2);
+  int prow[4];
+  double u[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    prow[k] = rmap[k0 + g + 4 * k];
+    u[k] = M[(size_t)prow[k] * ld + j];
+  }
+#pragma unroll
+  for (int cc = 0; cc < LU_NB - 1; ++cc) {
+    const double x = quad_bcast(u[cc >> 2], cc & 3);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (g + 4 * k > cc) u[k] = fma(-M[(size_t)prow[k] * ld + k0 + cc], x, u[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (g + 4 * k >= 1) M[(size_t)prow[k] * ld + j] = u[k];
+}
+
 // A22[:, jc .. jc+15] -= L21 U12[:, jc .. jc+15] for tile rows below j0, by
 // one wave on the matrix cores, two tile rows per step: operands
 // A[i][k] = -L21 in lane i + 16 k, B[k][j] = U12 in lane j + 16 k, the tile as
@@ -1244,9 +1280,9 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
     // the first of their blocks (column blocks bk = wave, wave + 3, ...;
     // bk == nblk is the right-hand side) here and the rest after the barrier
     if (wave == 0) {
-      lu_u12_block(M, ld, k0, pr, j0, 16, lane);
+      lu_u12_block16(M, ld, k0, rmap, j0, lane);
     } else if (wave <= nblk) {
-      if (wave < nblk) lu_u12_block(M, ld, k0, pr, j0 + 16 * wave, 16, lane);
+      if (wave < nblk) lu_u12_block16(M, ld, k0, rmap, j0 + 16 * wave, lane);
       else lu_u12_block(M, ld, k0, pr, np, 1, lane);
     }
     __syncthreads();
@@ -1263,7 +1299,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       for (int bk = wave; bk <= nblk; bk += 3) {
         if (bk < nblk) {
           if (bk > 3) {
-            lu_u12_block(M, ld, k0, pr, j0 + 16 * bk, 16, lane);
+            lu_u12_block16(M, ld, k0, rmap, j0 + 16 * bk, lane);
             wave_memory_sync();
           }
           lu_trail_rows(M, ld, rmap, k0, j0, nblk, j0 + 16 * bk, brow, lane, 0, 2);
