@@ -42,6 +42,15 @@ struct Tile {
   static_assert(JT * G == NJ, "order must split evenly");
 };
 
+// 1 / x for a finite nonzero x away from the exponent extremes: the hardware
+// reciprocal estimate and two Newton steps r <- r + r (1 - x r), within 1 ulp
+// (the correctly rounded division is a longer dependent sequence).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+
 // Natural logarithm of a positive normal x, from the classical series
 //   ln m = 2 atanh f = 2 (f + f^3/3 + f^5/5 + ...),  f = (m - 1) / (m + 1),
 // with x = m 2^e and the significand m in [1/sqrt 2, sqrt 2), so |f| < 0.172
@@ -56,11 +65,7 @@ __device__ __forceinline__ double log_series(double x) {
   const bool lo = m < 0.70710678118654752440;
   m = lo ? m + m : m;
   e = lo ? e - 1 : e;
-  const double den = m + 1.0;
-  double r = __builtin_amdgcn_rcp(den);  // reciprocal estimate, then two Newton steps
-  r = fma(fma(-den, r, 1.0), r, r);
-  r = fma(fma(-den, r, 1.0), r, r);
-  const double f = (m - 1.0) * r;
+  const double f = (m - 1.0) * recip(m + 1.0);
   const double f2 = f * f;
   double q = 1.0 / 25;
   q = fma(q, f2, 1.0 / 23);
@@ -381,7 +386,7 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     double Pa, Pb;
     if (KIND == GLUON) {
       const double lGz = sb + XG;
-      const double iw = 1.0 / w;
+      const double iw = BATCH ? 1.0 / w : recip(w);
       const double Qn = fma(fma(fma(fma(qc4, ck, qc3), ck, qc2), ck, qc1), ck, qc0);
       const double Qk = Qn * iw * iw;
       const double Mk = ymx * st2 * iw;
