@@ -815,19 +815,19 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
     ++r.n_jacobians;
     if (use_mix) ++r.n_jacobians_mixed;
     if (hipGetLastError() != hipSuccess) { status = DSE_E_DEVICE; break; }
-    HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, st));
+    // the solve also writes the full step c - Delta (the update kernel's FMA)
+    HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, st, d_c, 1.0, v.ct));
     const bool conv = f < o.tol;
     double rho = 1.0, ft = INFINITY, ft2 = INFINITY, dinf = 0.0;
+    int32_t flag = 0;
     for (int h = 0;; ++h) {
-      HIP_TRY(ctx, dse::launch_axpy(n, d_c, rho, v.dlt, v.ct, st));
+      if (h > 0) HIP_TRY(ctx, dse::launch_axpy(n, d_c, rho, v.dlt, v.ct, st));
       if ((s = eval_residual(ctx, v.ct, v.Ft, v.St)) != DSE_OK) { status = s; break; }
       ++r.n_residuals;
+      // the pivot flag arrives with the norms (one synchronisation)
+      if (h == 0) HIP_TRY(ctx, hipMemcpyAsync(&flag, v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       if ((s = read_norms(ctx, v.Ft, v.St, v.dlt, nrm)) != DSE_OK) { status = s; break; }
-      if (h == 0) {
-        int32_t flag = 0;
-        HIP_TRY(ctx, hipMemcpy(&flag, v.flag, sizeof(int32_t), hipMemcpyDeviceToHost));
-        if (flag == DSE_E_SINGULAR) { status = DSE_E_SINGULAR; set_err(ctx->err, "zero pivot"); break; }
-      }
+      if (h == 0 && flag == DSE_E_SINGULAR) { status = DSE_E_SINGULAR; set_err(ctx->err, "zero pivot"); break; }
       ft = isfinite(nrm[0]) ? nrm[0] : INFINITY;
       ft2 = isfinite(nrm[0]) && isfinite(nrm[3]) ? nrm[3] : INFINITY;
       dinf = nrm[2];
