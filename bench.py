@@ -146,18 +146,17 @@ def bench_adjoint(dse, workloads, torch) -> dict:
     Newton matrix at the root, one transposed LU solve, one parameter VJP)
     against central differences of full re-solves (four Newton solves, h = 1e-6),
     both after the same converged solve."""
-    from paper_1206_1779_amd.adjoint import chebyshev_basis
     cfg = workloads.config("cfg5")
     s = dse.Solver(**cfg)
-    B = chebyshev_basis(s, workloads.adjoint_loss_points(), "Z")
-    nz = cfg["n_z"]
+    pts = torch.as_tensor(workloads.adjoint_loss_points(), dtype=torch.float64, device="cuda:0")
     r = s.newton()
     c = r.c
 
     def ift():
-        lnz = B @ c[:nz]
-        gc = torch.zeros_like(c)
-        gc[:nz] = 2.0 * (lnz @ B)
+        # dL/dc = sum_m 2 ln Z(p_m) d ln Z(p_m)/dc (dse_running_coupling, dse_dressing_vjp),
+        # then J^T lambda = dL/dc and dL/dtheta = -lambda^T dF/dtheta
+        _, lnz, _ = s.running_coupling(c, pts)
+        gc = s.dressing_vjp(pts, 2.0 * lnz, None)
         J = s.jacobian(c, with_F=False)
         lam = s.lu_solve(J, gc, trans=True)
         _, ut = s.vjp(c, lam, with_c=False)
@@ -166,7 +165,8 @@ def bench_adjoint(dse, workloads, torch) -> dict:
     def loss(alpha, g0_inv):
         s.set_physics(alpha_mu=alpha, g0_inv=g0_inv)
         rr = s.newton(c0=c)
-        return float(((B @ rr.c[:nz]) ** 2).sum())
+        _, lnz, _ = s.running_coupling(rr.c, pts)
+        return float((lnz ** 2).sum())
 
     ift()
     loss(cfg["alpha_mu"], cfg["g0_inv"])  # first use of the loss's own kernels outside the timing

@@ -176,6 +176,21 @@ dse_status dse_jacobian_fd(dse_ctx* ctx, const double* d_c, double* d_J, double 
 dse_status dse_running_coupling(dse_ctx* ctx, const double* d_c, const double* d_u, int32_t m, double* d_alpha,
                                 double* d_lnZ, double* d_lnG);
 
+/* Vector-Jacobian product of the dressings at m momenta u > 0 with respect to
+ * the coefficients (Sec. 3 expansion in Chebyshev polynomials of the mapped
+ * momentum; the IR power laws and UV logarithms used outside [eps2, lambda2]
+ * are matched at the interval ends and do not depend on the coefficients, so
+ * d ln Z(u)/d a_j = d ln G(u)/d b_j = Tilde-T_j(s(u)), s clamped to [-1, 1]):
+ *   d_grad[j]       = sum_i d_wZ[i] d ln Z(u_i) / d a_j    (j < n_z)
+ *   d_grad[n_z + j] = sum_i d_wG[i] d ln G(u_i) / d b_j    (j < n_g)
+ * For a loss L(ln Z(u_i), ln G(u_i)) the weights are dL/d ln Z(u_i) and
+ * dL/d ln G(u_i), and d_grad is dL/dc.  d_u [m], d_wZ [m], d_wG [m] (either
+ * weight vector nullable: that half of d_grad is zero) and d_grad [n] on the
+ * device; enqueued on the context's stream.  m < 0, d_grad NULL, or d_u NULL
+ * with m > 0: DSE_E_INVALID. */
+dse_status dse_dressing_vjp(dse_ctx* ctx, const double* d_u, int32_t m, const double* d_wZ, const double* d_wG,
+                            double* d_grad);
+
 /* Solves F(c) = 0 by the under-relaxed Newton iteration of Sec. 3 starting
  * from d_c (overwritten by the last iterate).  opts may be NULL (tol 1e-10,
  * max_iter 60, extra_iters 0, max_halvings 30, step_tol 1e-14); h_report

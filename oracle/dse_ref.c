@@ -35,6 +35,8 @@
 #endif
 
 #define REF_PI 3.14159265358979323846264338327950288
+/* largest Gauss-Legendre rule the grid builder takes (nodes per panel) */
+#define GL_MAX 4096
 
 static int g_reversed = 0;
 static int g_threads = 0;
@@ -244,7 +246,9 @@ int dse_ref_grid_sizes(const dse_ref_params* p, int32_t* nq, int32_t* nk) {
 
 static int check_params(const dse_ref_params* p) {
   if (p->n_z < 1 || p->n_g < 1 || p->n_z > 1024 || p->n_g > 1024) return 1;
+  /* the grid builder's Gauss-Legendre scratch holds GL_MAX nodes per rule */
   if (p->n_rad < 1 || p->n_ir < 0 || p->n_ang < 1) return 1;
+  if (p->n_rad > GL_MAX || p->n_ir > GL_MAX || p->n_ang > GL_MAX) return 1;
   if (!(p->eps2 > 0.0) || !(p->lambda2 > p->eps2)) return 1;
   if (!(p->alpha_mu > 0.0) || !(p->n_c > 0.0)) return 1;
   if (p->n_ir > 0 && !(p->ir_efolds > 0.0)) return 1;
@@ -259,8 +263,8 @@ int dse_ref_grid(const dse_ref_params* p, double* y, double* W, double* theta, d
                  double* x_z, double* x_g) {
   if (check_params(p)) return 1;
   double lo = log(p->eps2), hi = log(p->lambda2);
-  double* u = (double*)malloc(sizeof(double) * 4096);
-  double* wu = (double*)malloc(sizeof(double) * 4096);
+  double* u = (double*)malloc(sizeof(double) * GL_MAX);
+  double* wu = (double*)malloc(sizeof(double) * GL_MAX);
   int q = 0;
   if (p->n_ir > 0) {
     dse_ref_gauss_legendre(p->n_ir, u, wu);

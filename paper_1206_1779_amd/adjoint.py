@@ -11,8 +11,6 @@ torch.autograd.
 """
 from __future__ import annotations
 
-import math
-
 import torch
 
 from . import dse as _dse
@@ -47,18 +45,23 @@ class ImplicitSolve(torch.autograd.Function):
         return -ut.to(ctx.theta_device), None, None, None
 
 
-def chebyshev_basis(solver: "_dse.Solver", points, which: str = "Z") -> torch.Tensor:
-    """Matrix B[m, j] = Tilde-T_j(s(p_m)) (Sec. 3 expansion, c_0/2 convention)
-    so that ln Z(p_m) = B @ a (or ln G(p_m) = B @ b) for points inside
-    [eps2, lambda2]."""
-    p = solver.p
-    n = p.n_z if which == "Z" else p.n_g
-    x = torch.as_tensor(points, dtype=torch.float64, device=solver.device)
-    L0 = 0.5 * (math.log(p.eps2) + math.log(p.lambda2))
-    L1 = 0.5 * (math.log(p.lambda2) - math.log(p.eps2))
-    s = ((torch.log(x) - L0) / L1).clamp(-1.0, 1.0)
-    cols = [torch.ones_like(s), s]  # T_0, T_1; the recurrence needs T_0 = 1
-    for _ in range(2, n):
-        cols.append(2.0 * s * cols[-1] - cols[-2])
-    cols[0] = torch.full_like(s, 0.5)  # Tilde-T_0 = 1/2
-    return torch.stack(cols[:n], dim=1)
+class DressingsAt(torch.autograd.Function):
+    """(ln Z(u), ln G(u)) = DressingsAt.apply(c, solver, u): the dressings at
+    momenta u from the coefficients c (dse_running_coupling), differentiable in
+    c through dse_dressing_vjp (d ln Z(u)/d a_j = d ln G(u)/d b_j =
+    Tilde-T_j(s(u)), Sec. 3 expansion).  Both directions run in the HIP
+    library; this class only wires them into torch.autograd."""
+
+    @staticmethod
+    def forward(ctx, c, solver, u):
+        u = torch.as_tensor(u, dtype=torch.float64).to(solver.device).contiguous().reshape(-1)
+        _, lnz, lng = solver.running_coupling(c.detach(), u)
+        ctx.solver = solver
+        ctx.save_for_backward(u)
+        return lnz, lng
+
+    @staticmethod
+    def backward(ctx, g_lnz, g_lng):
+        (u,) = ctx.saved_tensors
+        gc = ctx.solver.dressing_vjp(u, g_lnz, g_lng)
+        return gc, None, None

@@ -614,6 +614,19 @@ dse_status dse_running_coupling(dse_ctx* ctx, const double* d_c, const double* d
   return DSE_OK;
 }
 
+dse_status dse_dressing_vjp(dse_ctx* ctx, const double* d_u, int32_t m, const double* d_wZ, const double* d_wG,
+                            double* d_grad) {
+  if (!ctx) return DSE_E_INVALID;
+  if (m < 0 || !d_grad || (m > 0 && !d_u)) {
+    set_err(ctx->err, "m must be >= 0, d_grad non-NULL and d_u non-NULL when m > 0");
+    return DSE_E_INVALID;
+  }
+  DeviceGuard dg(ctx->device);
+  HIP_TRY(ctx, dse::launch_dressing_vjp(ctx->v, ctx->ph, d_u, m, m > 0 ? d_wZ : nullptr, m > 0 ? d_wG : nullptr,
+                                        d_grad, ctx->st));
+  return DSE_OK;
+}
+
 dse_status dse_jacobian_fd(dse_ctx* ctx, const double* d_c, double* d_J, double h_rel) {
   if (!ctx) return DSE_E_INVALID;
   if (!d_c || !d_J) { set_err(ctx->err, "d_c and d_J must not be NULL"); return DSE_E_INVALID; }
@@ -690,6 +703,13 @@ dse_status dse_set_physics(dse_ctx* ctx, double alpha_mu, double g0_inv, double 
   if (s != DSE_OK) return s;
   ctx->p = p;
   ctx->ph = make_phys(p);
+  // the recorded Newton step carries the physics constants as kernel
+  // arguments: record it again on the next dse_newton_step
+  if (ctx->step_exec) {
+    DeviceGuard dg(ctx->device);
+    (void)hipGraphExecDestroy(ctx->step_exec);
+    ctx->step_exec = nullptr;
+  }
   return DSE_OK;
 }
 

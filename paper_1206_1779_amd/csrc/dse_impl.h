@@ -124,6 +124,8 @@ hipError_t launch_norms(const Views& v, const double* F, const double* S, const 
                         double* out, hipStream_t st);
 hipError_t launch_coupling(const Views& v, const Phys& ph, double alpha_mu, const double* c, const double* u, int m,
                            double* alpha, double* lnZ, double* lnG, hipStream_t st);
+hipError_t launch_dressing_vjp(const Views& v, const Phys& ph, const double* u, int m, const double* wZ,
+                               const double* wG, double* grad, hipStream_t st);
 hipError_t launch_fd_shift(int n, const double* c, int j, double h_rel, double sgn, double* cs, double* hbuf,
                            hipStream_t st);
 hipError_t launch_fd_column(int n, const double* Fp, const double* Fm, const double* hbuf, int j, double* J,

@@ -24,7 +24,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "HIP device error", 3: "workspace t
 
 EXPORTS = [
     "dse_params_default", "dse_workspace_bytes", "dse_init", "dse_destroy", "dse_start_guess",
-    "dse_residual", "dse_jacobian", "dse_jacobian_fd", "dse_running_coupling", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
+    "dse_residual", "dse_jacobian", "dse_jacobian_fd", "dse_running_coupling", "dse_dressing_vjp", "dse_newton_solve", "dse_lu_solve", "dse_status_string",
     "dse_last_error", "dse_sizes", "dse_set_timing", "dse_read_timings", "dse_vjp",
     "dse_set_physics", "dse_newton_step", "dse_set_graphs",
     "dse_batch_workspace_bytes", "dse_batch_init", "dse_batch_destroy", "dse_batch_last_error",
@@ -92,6 +92,7 @@ def load():
             "dse_jacobian": (C.c_int, [vp, vp, vp, vp]),
             "dse_jacobian_fd": (C.c_int, [vp, vp, vp, C.c_double]),
             "dse_running_coupling": (C.c_int, [vp, vp, vp, C.c_int32, vp, vp, vp]),
+            "dse_dressing_vjp": (C.c_int, [vp, vp, C.c_int32, vp, vp, vp]),
             "dse_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
             "dse_lu_solve": (C.c_int, [vp, vp, vp, vp, C.c_int32]),
             "dse_status_string": (C.c_char_p, [C.c_int]),
@@ -254,6 +255,25 @@ class Solver:
             self._check(self.lib.dse_running_coupling(self.h, _ptr(c), _ptr(u), int(u.numel()),
                                                        _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))
         return tuple(out)
+
+    def dressing_vjp(self, u, wZ=None, wG=None) -> torch.Tensor:
+        """dL/dc for weights wZ = dL/d ln Z(u), wG = dL/d ln G(u) at the momenta
+        u (dse_dressing_vjp); either weight may be None."""
+        u = torch.as_tensor(u, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+        m = int(u.numel())
+
+        def w(x):
+            if x is None:
+                return None
+            x = torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+            if x.numel() != m:
+                raise ValueError("weights must have one entry per momentum")
+            return x
+        wZ, wG = w(wZ), w(wG)
+        g = self._vec()
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_dressing_vjp(self.h, _ptr(u), m, _ptr(wZ), _ptr(wG), _ptr(g)))
+        return g
 
     def lu_solve(self, J, b, trans: bool = False) -> torch.Tensor:
         J = torch.as_tensor(J, dtype=torch.float64).to(self.device).contiguous()

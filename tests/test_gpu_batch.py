@@ -153,3 +153,99 @@ def test_batch_family_256(ref, dse):
         _note("  problem %d (n_z %d n_g %d G0 %.2f): diff to single %.2e, bound %.2e"
               % (i, cfg["n_z"], cfg["n_g"], 1 / cfg["g0_inv"], err, bound))
         assert err <= 2 * bound  # both sides at their rounding floor
+
+
+# Members whose padded orders are 48 and 64: the order-48 and order-64 bodies
+# of the batch point kernel (the ones the 256-problem family runs), on a grid
+# small enough for the oracle to check every entry.
+WIDE_FAMILY = [
+    dict(n_z=48, n_g=64, g0_inv=0.1),
+    dict(n_z=64, n_g=40, g0_inv=0.03),
+    dict(n_z=40, n_g=48, g0_inv=0.2),
+    dict(n_z=33, n_g=20, g0_inv=1 / 15.0),
+    dict(n_z=20, n_g=30, g0_inv=0.05),
+]
+
+
+def _wide():
+    return [workloads.config("cfg1", n_rad=60, n_ir=8, n_ang=10, **d) for d in WIDE_FAMILY]
+
+
+def test_batch_orders_48_64_small_grid(ref, dse):
+    """Every Newton-matrix and residual entry of members with padded orders 48
+    and 64 against the oracle, for the per-item and the persistent launch at
+    one and two angular slices; one member's root against the oracle's."""
+    cfgs = _wide()
+    b = dse.Batch(cfgs)
+    c0 = b.start_guess()
+    pert = np.concatenate([workloads.perturbation(d["n_z"], d["n_g"], 0.03, seed=70 + i)
+                           for i, d in enumerate(cfgs)])
+    c = _np(c0) + pert
+    for slices, blocks in ((1, 0), (2, 48), (1, 300)):
+        _note("orders 48/64 small grid: slices=%d blocks=%d" % (slices, blocks))
+        b.set_launch(slices, blocks, 1)
+        J, F = b.jacobian(c)
+        J, F = _np(J), _np(F)
+        for i, cfg in enumerate(cfgs):
+            n = cfg["n_z"] + cfg["n_g"]
+            _check_JF(ref, cfg, c[b.off_c[i]: b.off_c[i + 1]],
+                      J[b.off_J[i]: b.off_J[i + 1]].reshape(n, n), F[b.off_c[i]: b.off_c[i + 1]])
+    b.set_launch(1, 0, 1)
+    _, res = b.newton(extra_iters=2)
+    for i in (0, 1):
+        p = ref.params(**cfgs[i])
+        cr, rr = ref.newton(p, extra_iters=2)
+        assert res[i].status == 0 and rr["status"] == 0
+        Jr = ref.jacobian(p, cr)
+        bound = 2.0 ** -53 * np.max(np.abs(np.linalg.inv(Jr)) @ ref.residual_scale(p, cr))
+        err = np.max(np.abs(_np(res[i].c) - cr))
+        _note("  member %d: iters %d (oracle %d), diff %.2e, bound %.2e"
+              % (i, res[i].iters, rr["iters"], err, bound))
+        assert abs(res[i].iters - rr["iters"]) <= 1
+        assert err <= bound
+
+
+def _cfg4_members():
+    """Members of the 256-problem family (grid 256+64 x 64) covering the
+    padded orders 48 and 64: the first member of each (N_Z, N_G) pair below."""
+    fam = workloads.family(256)
+    want = [(48, 64), (64, 48), (48, 48), (64, 64), (32, 48)]
+    out = []
+    for pair in want:
+        i = next(k for k, f in enumerate(fam) if (f["n_z"], f["n_g"]) == pair)
+        out.append((i, fam[i]))
+    return out
+
+
+def test_batch_family_members_full_grid_vs_oracle(ref, dse):
+    """Family members with N_Z, N_G in {48, 64} on the family's own grid
+    (256+64 radial x 64 angular), batched with the family's launch forms:
+    every F entry and every J entry against the oracle, and three converged
+    roots against the oracle's roots within the componentwise bound."""
+    members = _cfg4_members()
+    cfgs = [f for _, f in members]
+    b = dse.Batch(cfgs)
+    c = _np(b.start_guess())
+    for slices, blocks in ((1, 512), (2, 0)):
+        _note("family members full grid: slices=%d blocks=%d" % (slices, blocks))
+        b.set_launch(slices, blocks, 1)
+        J, F = b.jacobian(c)
+        J, F = _np(J), _np(F)
+        for i, cfg in enumerate(cfgs):
+            n = cfg["n_z"] + cfg["n_g"]
+            _note("  member %d (n_z %d n_g %d)" % (members[i][0], cfg["n_z"], cfg["n_g"]))
+            _check_JF(ref, cfg, c[b.off_c[i]: b.off_c[i + 1]],
+                      J[b.off_J[i]: b.off_J[i + 1]].reshape(n, n), F[b.off_c[i]: b.off_c[i + 1]])
+    b.set_launch(1, 512, 1)
+    _, res = b.newton(extra_iters=2)
+    for i in (0, 1, 3):
+        p = ref.params(**cfgs[i])
+        cr, rr = ref.newton(p, extra_iters=2)
+        assert res[i].status == 0 and rr["status"] == 0
+        Jr = ref.jacobian(p, cr)
+        bound = 2.0 ** -53 * np.max(np.abs(np.linalg.inv(Jr)) @ ref.residual_scale(p, cr))
+        err = np.max(np.abs(_np(res[i].c) - cr))
+        _note("  member %d root: iters %d (oracle %d), diff %.2e, bound %.2e"
+              % (members[i][0], res[i].iters, rr["iters"], err, bound))
+        assert abs(res[i].iters - rr["iters"]) <= 1
+        assert err <= bound

@@ -551,3 +551,108 @@ def test_root_rounding_floor_below_condition_bound(ref):
     assert r["status"] == 0
     assert shift <= bound
     assert shift > 1e-13 * np.max(np.abs(c0))
+
+
+def _rows_small(ref):
+    cfg = workloads.config("cfg1", n_z=4, n_g=5, n_rad=12, n_ir=4, n_ang=6, g0_inv=0.1)
+    p = ref.params(**cfg)
+    c = ref.start_guess(p) + workloads.perturbation(p.n_z, p.n_g, 0.05, seed=9)
+    return p, c
+
+
+def test_residual_scale_from_integrand_pieces(ref):
+    """S_r = |direct term| + |parameter| + sum |integrand| at x_r + sum
+    |integrand| at the subtraction point, recomputed here point by point from
+    the pinned building blocks (grid, dressings, kernels M and Q, the
+    integrands of Sec. 2), against dse_ref_residual_scale on a small grid."""
+    p, c = _rows_small(ref)
+    g = ref.grid(p)
+    a, b = c[:p.n_z], c[p.n_z:]
+    C = p.alpha_mu * p.n_c / (2 * math.pi ** 2)
+    e1, e2 = -2 - 6 * p.delta, -3 * p.delta
+
+    def abs_pieces(x, kind):
+        tot = 0.0
+        for yq, Wq in zip(g.y, g.W):
+            for th, vk in zip(g.theta, g.v):
+                z = ref.momentum_z(x, yq, th)
+                st2 = math.sin(th) ** 2
+                if kind == "gluon":
+                    lgy, lgz = ref.lnG(p, b, yq), ref.lnG(p, b, z)
+                    lzy, lzz = ref.lnZ(p, a, yq), ref.lnZ(p, a, z)
+                    om = C / (3 * x) * Wq * vk * st2
+                    tot += abs(om * ref.kernel_Q(x, yq, th) * math.exp(e1 * (lgy + lgz) + e2 * (lzy + lzz)))
+                    tot += abs(om * ref.kernel_M(x, yq, th) * math.exp(lgy + lgz))
+                else:
+                    tot += abs(C * Wq * yq * vk * st2 * st2 * math.exp(ref.lnG(p, b, yq) + ref.lnZ(p, a, z)) / z ** 2)
+        return tot
+
+    S = ref.residual_scale(p, c)
+    sub_z, sub_g = abs_pieces(p.lambda2, "gluon"), abs_pieces(0.0, "ghost")
+    for r in range(p.n_z + p.n_g):
+        if r < p.n_z:
+            x = g.x_z[r]
+            want = math.exp(-ref.lnZ(p, a, x)) + p.z_lambda_inv + abs_pieces(x, "gluon") + sub_z
+        else:
+            x = g.x_g[r - p.n_z]
+            want = math.exp(-ref.lnG(p, b, x)) + p.g0_inv + abs_pieces(x, "ghost") + sub_g
+        assert abs(S[r] - want) <= 1e-12 * want, (r, S[r], want)
+
+
+def test_residual_scale_ghost_rows_equal_self_energy_magnitudes(ref):
+    """Every ghost integrand has one sign (-C W y v sin^4 G Z / z^2 < 0), so a
+    ghost row's scale is |G(x)^{-1}| + G(0)^{-1} + |Pi_G(x)| + |Pi_G(0)|, with
+    Pi_G from the self-energy routine pinned to its closed form."""
+    p, c = _rows_small(ref)
+    g = ref.grid(p)
+    b = c[p.n_z:]
+    S = ref.residual_scale(p, c)
+    pi0 = ref.pi_ghost(p, c, 0.0, g.y, g.W, g.theta, g.v)
+    for i, x in enumerate(g.x_g):
+        pix = ref.pi_ghost(p, c, x, g.y, g.W, g.theta, g.v)
+        want = math.exp(-ref.lnG(p, b, x)) + p.g0_inv + abs(pix) + abs(pi0)
+        assert abs(S[p.n_z + i] - want) <= 1e-13 * want
+
+
+@pytest.mark.parametrize("name,max_iter", [("cfg1", 20), ("cfg2", 2)])
+def test_newton_from_unit_dressings_stalls(ref, name, max_iter):
+    """From c = 0 (G = Z = 1 on [eps2, Lambda^2]) the Newton direction is no
+    descent direction of the scaled residual: the relaxation collapses below
+    1e-6 and the merit stays above 0.5, which is why the solves start from
+    the asymptotic forms instead (the start from the asymptotic forms
+    converges, see the solution-level pins)."""
+    p = ref.params(**workloads.config(name))
+    c, rep = ref.newton(p, c0=np.zeros(p.n_z + p.n_g), max_iter=max_iter)
+    assert rep["status"] == 5
+    assert min(rep["fnorm_hist"]) > 0.5
+    assert max(rep["relax_hist"]) < 1e-6
+
+
+def test_stored_oracle_roots_solve_the_equations(ref):
+    """The stored roots (tests/golden/oracle_roots.json, written by the
+    committed script beside it from the oracle only) satisfy the oracle's
+    equations componentwise at N = 16 and 64, with the recorded sizes."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_roots.json")))
+    for name in ("cfg1", "cfg2"):
+        cfg = workloads.config(name)
+        assert gold[name]["config"] == cfg
+        p = ref.params(**cfg)
+        c = np.array(gold[name]["c"])
+        F = ref.residual(p, c)
+        S = ref.residual_scale(p, c)
+        assert np.max(np.abs(F) / S) < 1e-13
+        assert 0 < gold[name]["floor"] < gold[name]["bound"]
+    assert len(gold["cfg3"]["c"]) == 256 and gold["cfg3"]["scaled_residual"] < 1e-13
+
+
+@pytest.mark.parametrize("bad", [dict(n_rad=5000), dict(n_ir=4097), dict(n_ang=4097), dict(n_rad=0)])
+def test_grid_sizes_beyond_the_rule_scratch_are_rejected(ref, bad):
+    """Radial, IR and angular rules are limited to 4096 nodes each (the grid
+    builder's scratch); larger requests are refused, not written past it."""
+    p = ref.params(**workloads.config("cfg1", **bad))
+    with pytest.raises(ValueError):
+        ref.grid(p)
+    with pytest.raises(ref.OracleError):
+        ref.residual(p, np.zeros(p.n_z + p.n_g))
