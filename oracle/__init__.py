@@ -73,6 +73,10 @@ def load():
         P = C.POINTER(Params)
         sig = {
             "dse_ref_gauss_legendre": (C.c_int, [C.c_int, _D, _D]),
+            "dse_ref_gl_node": (C.c_int, [C.c_int, C.c_int, _D, _D]),
+            "dse_ref_renorm_scale": (C.c_int, [P, _D, C.c_int, _D]),
+            "dse_ref_schwinger_nodes": (C.c_int, [C.c_int, C.c_double, _D, _D]),
+            "dse_ref_schwinger": (C.c_int, [P, _D, C.c_int, C.c_double, _D, C.c_int, _D]),
             "dse_ref_cheb": (None, [C.c_double, C.c_int, _D]),
             "dse_ref_map": (C.c_double, [P, C.c_double]),
             "dse_ref_lnZ": (C.c_double, [P, _D, C.c_double]),
@@ -152,6 +156,14 @@ def gauss_legendre(n: int):
     return x, w
 
 
+def gl_node(n: int, i: int):
+    """Node i (ascending) of the n-point rule and its weight, computed alone."""
+    x = C.c_double(); w = C.c_double()
+    if load().dse_ref_gl_node(n, i, C.byref(x), C.byref(w)):
+        raise ValueError("bad n or i")
+    return x.value, w.value
+
+
 def cheb(s: float, n: int) -> np.ndarray:
     out = np.zeros(n)
     load().dse_ref_cheb(float(s), n, out.ctypes.data_as(_D))
@@ -177,6 +189,34 @@ def running_coupling(p: Params, c, u: float) -> float:
     dressings lnG, lnZ above (series plus IR / UV extension)."""
     c = np.asarray(c, dtype=np.float64)
     return p.alpha_mu * math.exp(2.0 * lnG(p, c[p.n_z:], u) + lnZ(p, c[:p.n_z], u))
+
+
+def renorm_scale(p: Params, c, scan: int = 4096) -> float:
+    """mu^2 with G^2(mu^2) Z(mu^2) = 1 (Sec. 2.1 footnote), the largest root in
+    [eps2, lambda2]; NaN when there is none."""
+    c, pc = _arr(c)
+    mu2 = C.c_double()
+    load().dse_ref_renorm_scale(C.byref(p), pc, int(scan), C.byref(mu2))
+    return mu2.value
+
+
+def schwinger_nodes(n: int, p_max: float):
+    """The mapped rule of the Schwinger function: p_i = p_max ((1 + x_i)/2)^2
+    and weights W_i over the n Gauss-Legendre nodes x_i."""
+    pn = np.zeros(n); W = np.zeros(n)
+    _check(load().dse_ref_schwinger_nodes(n, float(p_max), pn.ctypes.data_as(_D), W.ctypes.data_as(_D)),
+           "schwinger_nodes")
+    return pn, W
+
+
+def schwinger(p: Params, c, t, n: int = 1 << 17, p_max: float = 1e3) -> np.ndarray:
+    """Delta(t) = (1/pi) int_0^p_max dp cos(t p) Z(p^2)/p^2 (Sec. 2.2) at each t."""
+    c, pc = _arr(c)
+    t, pt = _arr(np.atleast_1d(t))
+    out = np.zeros(len(t))
+    _check(load().dse_ref_schwinger(C.byref(p), pc, int(n), float(p_max), pt, len(t), out.ctypes.data_as(_D)),
+           "schwinger")
+    return out
 
 
 def kernel_Q(x, y, theta):

@@ -66,41 +66,50 @@ static double kval(const ksum* k) { return k->s + k->c; }
 
 /* ------------------------------------------------------------------------ */
 /* Gauss-Legendre rule: Newton iteration on P_n from the three-term
- * recurrence (n+1) P_{n+1} = (2n+1) s P_n - n P_{n-1}.                      */
-int dse_ref_gauss_legendre(int n, double* nodes, double* weights) {
-  if (n < 1) return 1;
-  for (int i = 0; i < n; ++i) {
-    /* i-th root counted from +1 downwards */
-    double s = cos(REF_PI * (i + 0.75) / (n + 0.5));
-    double dp = 1.0;
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = s;
+ * recurrence (n+1) P_{n+1} = (2n+1) s P_n - n P_{n-1}.  One node at a time:
+ * node i (ascending order) and its weight.                                 */
+int dse_ref_gl_node(int n, int i, double* node, double* weight) {
+  if (n < 1 || i < 0 || i >= n) return 1;
+  /* root counted from +1 downwards */
+  const int r = n - 1 - i;
+  double s = cos(REF_PI * (r + 0.75) / (n + 0.5));
+  double dp = 1.0;
+  for (int it = 0; it < 100; ++it) {
+    double p0 = 1.0, p1 = s;
+    for (int k = 1; k < n; ++k) {
+      double p2 = ((2.0 * k + 1.0) * s * p1 - k * p0) / (k + 1.0);
+      p0 = p1;
+      p1 = p2;
+    }
+    if (n == 1) { p1 = s; p0 = 1.0; }
+    /* P_n'(s) = n (s P_n - P_{n-1}) / (s^2 - 1) */
+    dp = n * (s * p1 - p0) / (s * s - 1.0);
+    double ds = p1 / dp;
+    s -= ds;
+    if (fabs(ds) < 1e-16) {
+      /* one more pass to settle the derivative at the final node */
+      p0 = 1.0; p1 = s;
       for (int k = 1; k < n; ++k) {
         double p2 = ((2.0 * k + 1.0) * s * p1 - k * p0) / (k + 1.0);
         p0 = p1;
         p1 = p2;
       }
       if (n == 1) { p1 = s; p0 = 1.0; }
-      /* P_n'(s) = n (s P_n - P_{n-1}) / (s^2 - 1) */
       dp = n * (s * p1 - p0) / (s * s - 1.0);
-      double ds = p1 / dp;
-      s -= ds;
-      if (fabs(ds) < 1e-16) {
-        /* one more pass to settle the derivative at the final node */
-        p0 = 1.0; p1 = s;
-        for (int k = 1; k < n; ++k) {
-          double p2 = ((2.0 * k + 1.0) * s * p1 - k * p0) / (k + 1.0);
-          p0 = p1;
-          p1 = p2;
-        }
-        if (n == 1) { p1 = s; p0 = 1.0; }
-        dp = n * (s * p1 - p0) / (s * s - 1.0);
-        break;
-      }
+      break;
     }
-    nodes[n - 1 - i] = s;
-    weights[n - 1 - i] = 2.0 / ((1.0 - s * s) * dp * dp);
   }
+  *node = s;
+  *weight = 2.0 / ((1.0 - s * s) * dp * dp);
+  return 0;
+}
+
+/* All n nodes, ascending (each node independently, so the threads change
+ * nothing in the result). */
+int dse_ref_gauss_legendre(int n, double* nodes, double* weights) {
+  if (n < 1) return 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(dse_ref_get_threads()) if (n >= 2048)
+  for (int i = 0; i < n; ++i) dse_ref_gl_node(n, i, &nodes[i], &weights[i]);
   return 0;
 }
 
@@ -812,5 +821,92 @@ int dse_ref_start_guess(const dse_ref_params* p, double* c) {
     }
     free(T);
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Renormalisation scale (Sec. 2.1 footnote): mu^2 is where the running
+ * coupling alpha(x) = alpha(mu^2) G^2(x) Z(x) equals alpha(mu^2), i.e. the
+ * root of h(x) = 2 ln G(x) + ln Z(x).  Of several roots in [eps2, lambda2]
+ * the largest is taken (the perturbative side: a decoupling solution's
+ * alpha(x) also rises through alpha(mu^2) in the infrared).  The search runs
+ * in the mapped variable s: a scan of `scan` equal intervals from s = 1
+ * downwards finds the first sign change, bisection narrows it to adjacent
+ * doubles.  Returns 0 and *mu2, or 1 (no root; *mu2 = NaN). */
+static double renorm_h(const dse_ref_params* p, const double* c, double s) {
+  double u = exp(make_consts(p).L0 + make_consts(p).L1 * s);
+  if (s <= -1.0) u = p->eps2;
+  if (s >= 1.0) u = p->lambda2;
+  return 2.0 * dse_ref_lnG(p, c + p->n_z, u) + dse_ref_lnZ(p, c, u);
+}
+int dse_ref_renorm_scale(const dse_ref_params* p, const double* c, int scan, double* mu2) {
+  *mu2 = NAN;
+  if (check_params(p) || scan < 1) return 1;
+  double hi = 1.0, hhi = renorm_h(p, c, hi);
+  for (int k = scan - 1; k >= 0; --k) {
+    double lo = -1.0 + 2.0 * k / scan;
+    double hlo = renorm_h(p, c, lo);
+    if (hhi == 0.0) { *mu2 = exp(make_consts(p).L0 + make_consts(p).L1 * hi); return 0; }
+    if ((hlo < 0.0) != (hhi < 0.0) || hlo == 0.0) {
+      /* bisection on [lo, hi], h(lo) and h(hi) of opposite sign (or h(lo) = 0) */
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        double hm = renorm_h(p, c, mid);
+        if ((hm < 0.0) == (hhi < 0.0) && hm != 0.0) { hi = mid; hhi = hm; }
+        else { lo = mid; hlo = hm; }
+      }
+      double s = fabs(hlo) <= fabs(hhi) ? lo : hi;
+      *mu2 = exp(make_consts(p).L0 + make_consts(p).L1 * s);
+      return 0;
+    }
+    hi = lo;
+    hhi = hlo;
+  }
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Schwinger function of the gluon propagator (Sec. 2.2):
+ *   Delta(t) = (1/pi) int_0^inf dp cos(t p) sigma(p^2),  sigma = Z(p^2)/p^2,
+ * with a mapped Gauss-Legendre rule (Sec. 5): p = p_max ((1 + x)/2)^2 over the
+ * n nodes x_i of [-1, 1], dp = p_max (1 + x)/2 dx, so the rule covers
+ * [0, p_max] (the oscillating tail beyond p_max is left out; it is of order
+ * Z(p_max^2) / (t p_max^2)).  The square clusters the nodes towards p = 0,
+ * where sigma carries the infrared power law.                              */
+int dse_ref_schwinger_nodes(int n, double p_max, double* pn, double* Wn) {
+  if (n < 1 || !(p_max > 0.0)) return 1;
+  double* x = (double*)malloc(sizeof(double) * n);
+  double* w = (double*)malloc(sizeof(double) * n);
+  dse_ref_gauss_legendre(n, x, w);
+  for (int i = 0; i < n; ++i) {
+    double h = 0.5 * (1.0 + x[i]);
+    pn[i] = p_max * h * h;
+    Wn[i] = w[i] * p_max * h;
+  }
+  free(x); free(w);
+  return 0;
+}
+
+int dse_ref_schwinger(const dse_ref_params* p, const double* c, int n, double p_max, const double* t, int m,
+                      double* out) {
+  if (check_params(p) || n < 1 || m < 0 || !(p_max > 0.0)) return 1;
+  double* pn = (double*)malloc(sizeof(double) * n);
+  double* Wn = (double*)malloc(sizeof(double) * n);
+  double* g = (double*)malloc(sizeof(double) * n);
+  dse_ref_schwinger_nodes(n, p_max, pn, Wn);
+  /* per node: W_i sigma(p_i^2) / pi, the dressing from the expansion and its
+   * IR / UV extension */
+  for (int i = 0; i < n; ++i) {
+    double u = pn[i] * pn[i];
+    g[i] = Wn[i] * exp(dse_ref_lnZ(p, c, u)) / u / REF_PI;
+  }
+#pragma omp parallel for schedule(static) num_threads(dse_ref_get_threads()) if (m >= 4)
+  for (int j = 0; j < m; ++j) {
+    ksum acc = {0.0, 0.0};
+    for (int i = 0; i < n; ++i) kadd(&acc, g[i] * cos(t[j] * pn[i]));
+    out[j] = kval(&acc);
+  }
+  free(pn); free(Wn); free(g);
   return 0;
 }

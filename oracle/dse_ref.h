@@ -72,6 +72,8 @@ typedef struct {
 
 /* n-point Gauss-Legendre rule on [-1,1]: nodes ascending. */
 int dse_ref_gauss_legendre(int n, double* nodes, double* weights);
+/* Node i (ascending) of the same rule and its weight, computed alone. */
+int dse_ref_gl_node(int n, int i, double* node, double* weight);
 
 /* Tilde-T_j(s), j<n, with the c0/2 convention of Sec. 3 (Tilde-T_0 = 1/2). */
 void dse_ref_cheb(double s, int n, double* out);
@@ -138,6 +140,20 @@ int dse_ref_start_guess(const dse_ref_params* p, double* c);
 /* Newton iteration c <- c - rho J^{-1} F from the given c (Sec. 3). */
 int dse_ref_newton(const dse_ref_params* p, double* c, const dse_ref_newton_opts* o,
                    dse_ref_newton_report* rep);
+
+/* Renormalisation scale of Sec. 2.1 (footnote): the largest root mu2 in
+ * [eps2, lambda2] of G^2(x) Z(x) = 1, found by a scan of `scan` equal
+ * intervals in the mapped variable s (from s = 1 down) and bisection.
+ * Returns 0, or 1 when there is no root (*mu2 = NaN). */
+int dse_ref_renorm_scale(const dse_ref_params* p, const double* c, int scan, double* mu2);
+
+/* Schwinger function of the gluon propagator (Sec. 2.2),
+ * Delta(t) = (1/pi) int dp cos(t p) Z(p^2)/p^2, by the mapped Gauss-Legendre
+ * rule p = p_max ((1 + x)/2)^2 on n nodes (Sec. 5): out[j] = Delta(t[j]).
+ * dse_ref_schwinger_nodes gives the rule itself (p[n], weights W[n]). */
+int dse_ref_schwinger_nodes(int n, double p_max, double* p, double* W);
+int dse_ref_schwinger(const dse_ref_params* p, const double* c, int n, double p_max, const double* t, int m,
+                      double* out);
 
 /* Summation order of all quadrature sums: 0 forward, 1 reversed (used to
  * measure the oracle's own rounding floor). */

@@ -38,6 +38,12 @@ CONFIGS = {
     "cfg3": dict(n_z=128, n_g=128, n_rad=1024, n_ir=256, n_ang=128, eps2=1e-8, lambda2=1e8,
                  ir_efolds=40.0, alpha_mu=1.0, n_c=3.0, g0_inv=1.0 / 15.0,
                  z_lambda_inv=1.0 / Z_LAMBDA_1E8),
+    # the paper's own physics (Sec. 2.1): Lambda^2 = 5e4 GeV^2, eps^2 = 1e-6 GeV^2,
+    # Z(Lambda^2) = 0.256, alpha(mu^2) = 1, scaling solution; 24 coefficients per
+    # function on a 96+24 x 24 grid (the renormalisation scale, alpha(M_Z^2) and
+    # the Schwinger function are evaluated on its solution)
+    "paper": dict(n_z=24, n_g=24, n_rad=96, n_ir=24, n_ang=24, eps2=1e-6, lambda2=5e4,
+                  ir_efolds=40.0, alpha_mu=1.0, n_c=3.0, g0_inv=0.0, z_lambda_inv=1.0 / 0.256),
     # 5: adjoint configuration (same physics and grid as 2)
     "cfg5": dict(n_z=64, n_g=64, n_rad=256, n_ir=64, n_ang=64, eps2=1e-8, lambda2=1e8,
                  ir_efolds=40.0, alpha_mu=1.0, n_c=3.0, g0_inv=1.0 / 15.0,
@@ -50,7 +56,17 @@ WORKLOAD_NAMES = {
     "cfg3": "ghost-gluon DSE, N=128 per function, 1024+256 radial x 128 angular, G(0)=15",
     "cfg4": "ghost-gluon DSE family, 256 solves, N in {32,48,64}, 256+64 x 64, G(0) in [5,50]",
     "cfg5": "ghost-gluon DSE adjoint, N=64, 256+64 x 64, G(0)=15",
+    "paper": "ghost-gluon DSE at the paper's parameters, N=24, 96+24 x 24, Lambda^2=5e4, scaling",
 }
+
+#: Schwinger function workload (Sec. 2.2, Table 2): 2^17 mapped Gauss-Legendre
+#: nodes over p in [0, P], Euclidean times t = 0.02 k GeV^-1, k < 1024
+SCHWINGER = dict(n_nodes=1 << 17, p_max=1.0e3, n_t=1024, dt=0.02)
+
+
+def schwinger_times(n_t: int = SCHWINGER["n_t"], dt: float = SCHWINGER["dt"]) -> np.ndarray:
+    """Euclidean times t_k = k dt (GeV^-1), k < n_t."""
+    return dt * np.arange(n_t)
 
 
 def config(name: str, **overrides) -> dict:
