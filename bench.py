@@ -2,10 +2,11 @@
 
 A step is one Newton iteration of the N = 64 workload (64 Chebyshev
 coefficients per dressing function, 256+64 radial x 64 angular quadrature,
-decoupling G(0) = 15): Newton matrix and residual assembly (dressing, fused
-point kernels, B.T contraction on MFMA, assembly), the FP64 LU solve of
-J Delta = F, and the residual at c - Delta.  value = Newton-matrix entries
-(n^2 = 128^2) per second of step time.
+decoupling G(0) = 15): the FP64 LU solve of J Delta = F for the matrix held
+from the previous step, the update c - Delta, and the Newton matrix and
+residual assembly at the new point (dressing, fused point kernels, B.T
+contraction on MFMA, assembly), which the next step solves with.
+value = Newton-matrix entries (n^2 = 128^2) per second of step time.
 
 Beside it: seconds per Newton solve at N = 64, the 256-problem family solved
 batched against the plain path per problem, the implicit-function gradient
@@ -72,28 +73,60 @@ def measured_traffic(kernel: str):
 
 def cpu_baseline(cfg: dict, c, cpu_seconds: float = 20.0, max_steps: int = 50) -> dict:
     """The oracle (plain FP64 C, OpenMP over rows, all host threads) doing the
-    same step on the host, repeated until about `cpu_seconds` of CPU time
-    (wall time x threads) have been spent, at most max_steps times."""
+    same step on the host: LU solve of the held Newton matrix, update, Newton
+    matrix and residual at the new point; repeated until about `cpu_seconds` of
+    CPU time (wall time x threads) have been spent, at most max_steps times."""
     import numpy as np
     import oracle
     p = oracle.params(**cfg)
     c = np.asarray(c, dtype=np.float64)
     n = p.n_z + p.n_g
     threads = oracle.get_threads()
+    J, F = oracle.jacobian(p, c, with_F=True)  # the matrix the first step solves with
     steps = 0
     t0 = time.perf_counter()
     while True:
+        c = c - oracle.lu_solve(J, F)
         J, F = oracle.jacobian(p, c, with_F=True)
-        d = oracle.lu_solve(J, F)
-        oracle.residual(p, c - d)
         steps += 1
         dt = time.perf_counter() - t0
         if dt * threads >= cpu_seconds or steps >= max_steps:
             break
     return {"value": n * n * steps / dt, "unit": "Jacobian entries/s", "cores": threads,
             "kind": "oracle", "seconds": dt, "steps": steps,
-            "sample": "%d Newton iterations (J and F, LU solve, trial residual) of the N=64 "
-                      "workload at the start guess, %d host threads" % (steps, threads)}
+            "sample": "%d Newton iterations (LU solve, update, J and F at the new point) of the N=64 "
+                      "workload from the start guess, %d host threads" % (steps, threads)}
+
+
+def root_errors(c_gpu, gold: dict) -> dict:
+    """Error of converged coefficients against the oracle's root stored in
+    tests/golden/oracle_roots.json: largest absolute difference, largest
+    elementwise relative difference over |c_j| >= 1e-6 ||c||_inf, and the
+    componentwise condition bound and one-ulp floor stored with the root."""
+    import numpy as np
+    c = np.asarray(c_gpu, dtype=np.float64)
+    cr = np.asarray(gold["c"], dtype=np.float64)
+    big = np.abs(cr) >= 1e-6 * np.abs(cr).max()
+    return {"max_abs": float(np.abs(c - cr).max()),
+            "max_elementwise_rel": float((np.abs(c - cr)[big] / np.abs(cr)[big]).max()),
+            "bound": gold["bound"], "floor": gold["floor"]}
+
+
+def load_oracle_roots() -> dict:
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_roots.json")) as f:
+        return json.load(f)
+
+
+def bench_root_parity(dse, workloads, torch) -> dict:
+    """Converged FP64 coefficients at N = 16 and N = 64 (two full steps after
+    convergence, as the stored oracle roots) against the oracle's."""
+    gold = load_oracle_roots()
+    out = {}
+    for name in ("cfg1", "cfg2"):
+        s = dse.Solver(**workloads.config(name))
+        r = s.newton(extra_iters=2)
+        out[name] = dict(root_errors(r.c.cpu().numpy(), gold[name]), iters=r.iters)
+    return out
 
 
 def bench_batched(dse, workloads, torch) -> dict:
@@ -240,6 +273,61 @@ def bench_coupling(dse, workloads, torch) -> dict:
             "g0_inv": cfg["g0_inv"]}
 
 
+def bench_schwinger(dse, workloads, torch, with_cpu: bool = True) -> dict:
+    """The Schwinger function of the gluon propagator (Sec. 2.2; the paper's
+    second workload, Table 2): the scaling solution at the paper's parameters
+    (Lambda^2 = 5e4, Z(Lambda^2) = 0.256, alpha(mu^2) = 1), Delta(t) at 1024
+    times t = 0.02 k GeV^-1 by the 2^17-node mapped Gauss-Legendre rule
+    generated on the device (node generation included, as in Table 2); the
+    node generation alone; the first zero of Delta, mu^2 (G^2 Z = 1) and
+    alpha(M_Z^2).  The oracle is timed beside it on a smaller rule."""
+    import numpy as np
+    cfg = workloads.config("paper")
+    s = dse.Solver(**cfg)
+    c = s.newton(extra_iters=2).c
+    W = workloads.SCHWINGER
+    t = torch.as_tensor(workloads.schwinger_times(), dtype=torch.float64, device=c.device)
+    n = W["n_nodes"]
+    lib = dse.load()
+    ws = torch.empty(lib.dse_schwinger_workspace_bytes(n, t.numel()) + 256, dtype=torch.uint8, device=c.device)
+    s.schwinger(c, t, n=n, p_max=W["p_max"], ws=ws)  # warm-up
+    dse.gauss_legendre(n, device=c.device)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    d = s.schwinger(c, t, n=n, p_max=W["p_max"], ws=ws)
+    ev[1].record()
+    ev[2].record()
+    dse.gauss_legendre(n, device=c.device)
+    ev[3].record()
+    torch.cuda.synchronize()
+    d = d.cpu().numpy()
+    tt = workloads.schwinger_times()
+    k = int(np.where(np.diff(np.sign(d)) != 0)[0][0])
+    t0 = tt[k] - d[k] * (tt[k + 1] - tt[k]) / (d[k + 1] - d[k])
+    alpha_mz, _, _ = s.running_coupling(c, torch.tensor([91.2 ** 2], dtype=torch.float64, device=c.device))
+    out = {"workload": workloads.WORKLOAD_NAMES["paper"], "nodes": n, "times": int(t.numel()),
+           "p_max": W["p_max"], "total_ms": ev[0].elapsed_time(ev[1]),
+           "node_generation_ms": ev[2].elapsed_time(ev[3]), "first_zero_t": t0,
+           "mu2": s.renorm_scale(c), "alpha_mz2": float(alpha_mz.item()),
+           "paper_table2_s": {"GTX 560 Ti": 4.1, "Tesla C2070": 3.9, "Xeon X5650 sequential": 226.9}}
+    if with_cpu:
+        import oracle
+        p = oracle.params(**cfg)
+        nc = 1 << 14
+        tc0 = time.perf_counter()
+        oracle.gauss_legendre(nc)
+        t_gl = time.perf_counter() - tc0
+        tc0 = time.perf_counter()
+        oracle.schwinger(p, c.cpu().numpy(), tt, n=nc, p_max=W["p_max"])
+        t_all = time.perf_counter() - tc0
+        out["cpu_oracle"] = {"nodes": nc, "times": len(tt), "threads": oracle.get_threads(),
+                             "gl_s": t_gl, "total_s": t_all,
+                             "total_s_extrapolated_to_nodes": t_all + t_gl * ((n / nc) ** 2 - 1)
+                             + (t_all - t_gl) * (n / nc - 1)}
+    return out
+
+
 def bench_mixed(dse, workloads, torch) -> dict:
     """N = 128 per function, 1024+256 radial x 128 angular: the Newton matrix
     with FP32 derivative sums and FP32 MFMA contraction against FP64 (device
@@ -279,6 +367,9 @@ def bench_mixed(dse, workloads, torch) -> dict:
     dc = (roots["mixed"] - roots["fp64"]).abs()
     out["root_max_abs_diff"] = float(dc.max())
     out["root_max_rel_diff"] = float(dc.max() / roots["fp64"].abs().max())
+    gold = load_oracle_roots()["cfg3"]
+    for k in roots:
+        out["root_vs_oracle_" + k] = root_errors(roots[k].cpu().numpy(), gold)
     return out
 
 
@@ -316,22 +407,26 @@ def main() -> int:
     cfg = workloads.config(name)
     s = dse.Solver(device="cuda:0", **cfg)
     n = s.n
-    c = s.start_guess()
+    # the steps run at the solution (the work per step does not depend on c)
+    root = s.newton(tol=1e-10).c
+    bufs = (root.clone(), torch.empty_like(root))
+    F_out, S_out = torch.empty_like(root), torch.empty_like(root)
 
-    out = (torch.empty_like(c), torch.empty_like(c), torch.empty_like(c))
+    def step(k):
+        # one Newton iteration in the library: LU solve of the matrix held from
+        # the previous step, update, J and F at the new point; the coefficient
+        # buffers alternate, so from the second step on every step assembles once
+        src, dst = bufs[k % 2], bufs[(k + 1) % 2]
+        s.newton_step(src, 1.0, out=(dst, F_out, S_out))
 
-    def step(cv):
-        # one Newton iteration in the library: J and F, LU solve, update, trial residual
-        return s.newton_step(cv, 1.0, out=out)
-
-    # timed region: K steps replayed from the library's recorded graph
+    # timed region: K steps replayed from the library's recorded graphs
     s.set_graphs(True)
-    for _ in range(args.warmup):
-        step(c)
+    for k in range(args.warmup):
+        step(k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(c)
+    for k in range(args.warmup, args.warmup + args.steps):
+        step(k)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt / args.steps * 1e3
@@ -342,13 +437,14 @@ def main() -> int:
     s.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(c)
+    for k in range(args.steps):
+        step(k)
     torch.cuda.synchronize()
     dt_eager = time.perf_counter() - t0
     stages, cnt = s.read_timings()
     s.set_timing(False)
     s.set_graphs(True)
+    c = s.start_guess()
 
     # Jacobian assembly alone (device time of its five stages)
     t_asm = sum(stages) * 1e-3
@@ -383,7 +479,8 @@ def main() -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": workloads.WORKLOAD_NAMES[name], "n_z": cfg["n_z"], "n_g": cfg["n_g"],
                    "n_rad": cfg["n_rad"], "n_ir": cfg["n_ir"], "n_ang": cfg["n_ang"],
-                   "g0": 1.0 / cfg["g0_inv"], "step": "J+F assembly, LU solve, trial residual"},
+                   "g0": 1.0 / cfg["g0_inv"],
+                   "step": "LU solve of the held Newton matrix, update, J+F assembly at the new point"},
         "ms_per_step_without_graph": dt_eager / args.steps * 1e3,
         "assembly_entries_per_s": n * n / t_asm,
         "assembly_ms": t_asm * 1e3,
@@ -397,6 +494,8 @@ def main() -> int:
         out["mixed"] = bench_mixed(dse, workloads, torch)
         out["fd_jacobian"] = bench_fd(dse, workloads, torch)
         out["coupling"] = bench_coupling(dse, workloads, torch)
+        out["root_parity"] = bench_root_parity(dse, workloads, torch)
+        out["schwinger"] = bench_schwinger(dse, workloads, torch, with_cpu=not args.no_cpu)
     if not args.no_cpu:
         cb = cpu_baseline(cfg, c.cpu().numpy())
         cb["gpu_speedup"] = value / cb["value"]

@@ -191,6 +191,43 @@ dse_status dse_running_coupling(dse_ctx* ctx, const double* d_c, const double* d
 dse_status dse_dressing_vjp(dse_ctx* ctx, const double* d_u, int32_t m, const double* d_wZ, const double* d_wG,
                             double* d_grad);
 
+/* Renormalisation scale (Sec. 2.1 footnote: mu is fixed by the condition
+ * G^2(mu^2) Z(mu^2) = 1 for the given alpha(mu^2)): d_mu2[0] receives the
+ * largest root mu^2 in [eps2, lambda2] of 2 ln G(x) + ln Z(x) = 0 (where the
+ * running coupling alpha(x) = alpha(mu^2) G^2 Z passes alpha(mu^2) on its
+ * perturbative side; a decoupling solution's coupling also rises through it
+ * in the infrared), or NaN if there is none.  Found in the mapped variable s
+ * (Sec. 3) by a scan of 4096 equal intervals from s = 1 down and multisection
+ * to adjacent doubles.  d_c [n] and d_mu2 [1] on the device; enqueued on the
+ * context's stream. */
+dse_status dse_renorm_scale(dse_ctx* ctx, const double* d_c, double* d_mu2);
+
+/* Gauss-Legendre rule of n nodes on [-1, 1] (1 <= n <= 2^24) computed on the
+ * device: Newton's method on P_n with the three-term recurrence from
+ * Tricomi's estimate of each root, the weight 2 / ((1 - x^2) P_n'(x)^2) at the
+ * converged node (the node generation the paper parallelises for the
+ * Schwinger function, Sec. 5).  d_x [n] (ascending) and d_w [n] on the device;
+ * d_ws: device workspace of dse_gauss_legendre_workspace_bytes(n) bytes,
+ * 256-byte aligned (the recurrence coefficients).  Enqueued on hip_stream
+ * without synchronising.  Errors: DSE_E_INVALID (message in
+ * dse_last_error(NULL)), DSE_E_NOMEM for a short workspace. */
+size_t dse_gauss_legendre_workspace_bytes(int32_t n);
+dse_status dse_gauss_legendre(int32_t n, double* d_x, double* d_w, void* d_ws, size_t ws_bytes, void* hip_stream);
+
+/* Schwinger function of the gluon propagator (Sec. 2.2):
+ *   d_delta[j] = Delta(t_j) = (1/pi) int_0^p_max dp cos(t_j p) Z(p^2)/p^2,
+ * j < m, for the dressing Z of the coefficients d_c (expansion with its IR and
+ * UV extension), by the n-node Gauss-Legendre rule generated on the device
+ * (as dse_gauss_legendre) and mapped by p = p_max ((1 + x)/2)^2 (Sec. 5: a
+ * mapped Gauss-Legendre rule; the paper uses 2^17 nodes).  The oscillating
+ * tail beyond p_max is left out (of order Z(p_max^2) / (t p_max^2)).
+ * d_c [n_z + n_g], d_t [m] (GeV^-1 when momenta are in GeV), d_delta [m] on
+ * the device; d_ws: workspace of dse_schwinger_workspace_bytes(n, m) bytes,
+ * 256-byte aligned.  Enqueued on the context's stream. */
+size_t dse_schwinger_workspace_bytes(int32_t n, int32_t m);
+dse_status dse_schwinger(dse_ctx* ctx, const double* d_c, int32_t n, double p_max, const double* d_t, int32_t m,
+                         double* d_delta, void* d_ws, size_t ws_bytes);
+
 /* Solves F(c) = 0 by the under-relaxed Newton iteration of Sec. 3 starting
  * from d_c (overwritten by the last iterate).  opts may be NULL (tol 1e-10,
  * max_iter 60, extra_iters 0, max_halvings 30, step_tol 1e-14); h_report

@@ -1,30 +1,52 @@
-"""Builds the HIP library ``libdse.so`` for gfx950 in-tree with hipcc."""
+"""Builds the HIP library ``libdse.so`` for gfx950 in-tree with hipcc.
+
+Each source is compiled to an object in parallel (``_build/``), then the
+objects are linked into the shared library."""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdse.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("dse_host.hip", "dse_kernels.hip", "dse_batch.hip")]
+OBJDIR = os.path.join(HERE, "_build")
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("dse_host.hip", "dse_kernels.hip", "dse_batch.hip",
+                                                    "dse_observables.hip")]
 
 # Packed FP32 instructions are switched off for all device code.
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + SOURCES
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+    return res.stderr
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJDIR, exist_ok=True)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(OBJDIR, os.path.basename(s).replace(".hip", ".%s.o" % tag)) for s in SOURCES]
+    cmds = [[hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", "-o", o, s]
+            for s, o in zip(SOURCES, objs)]
+    try:
+        with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+            logs = list(ex.map(_run, cmds))
+        tmp = LIB + ".tmp" + tag
+        logs.append(_run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs))
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     if verbose:
-        print(res.stderr)
-    os.replace(tmp, LIB)
+        print("\n".join(l for l in logs if l))
     return LIB
 
 

@@ -15,35 +15,6 @@
 
 #include "dse_impl.h"
 
-struct dse_ctx {
-  dse_params p;
-  dse::Views v;
-  dse::Phys ph;
-  hipStream_t st;
-  int device;
-  char* ws;
-  size_t ws_bytes;
-  bool timing;
-  // event ring: per timed dse_jacobian, events before dressing, before the
-  // gluon point kernel, between gluon and ghost, after ghost, after the
-  // contraction, after the assembly
-  static constexpr int kRing = 64;
-  static constexpr int kEv = 6;
-  hipEvent_t ev[kRing][kEv];
-  int ring_count;
-  double acc_ms[5];
-  int acc_n;
-  // recorded Newton step (dse_newton_step): the launch sequence for one set
-  // of pointers and one relaxation, replayed as a HIP graph
-  bool graphs = true;
-  hipStream_t cap_st = nullptr;  // private stream the graph is recorded on (the
-                                 // caller's stream may be the null stream, which
-                                 // cannot be captured); replays go to st
-  hipGraphExec_t step_exec = nullptr;
-  const void* step_key[4] = {nullptr, nullptr, nullptr, nullptr};
-  double step_rho = 0.0;
-  char err[512];
-};
 
 static char g_init_err[512];
 
@@ -55,6 +26,8 @@ void set_err(char* buf, const char* fmt, ...) {
   vsnprintf(buf, 512, fmt, ap);
   va_end(ap);
 }
+
+char* global_err() { return g_init_err; }
 
 }  // namespace dse
 
@@ -558,7 +531,8 @@ dse_status dse_destroy(dse_ctx* ctx) {
   if (!ctx) return DSE_OK;
   for (auto& row : ctx->ev)
     for (auto& e : row) (void)hipEventDestroy(e);
-  if (ctx->step_exec) (void)hipGraphExecDestroy(ctx->step_exec);
+  for (auto& g : ctx->steps)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
   delete ctx;
   return DSE_OK;
@@ -634,6 +608,7 @@ dse_status dse_jacobian_fd(dse_ctx* ctx, const double* d_c, double* d_J, double 
   DeviceGuard dg(ctx->device);
   const dse::Views& v = ctx->v;
   double* hbuf = v.scal + 4;
+  ctx->jac_at = nullptr;  // the residuals below overwrite the held F and S
   for (int j = 0; j < v.n; ++j) {
     HIP_TRY(ctx, dse::launch_fd_shift(v.n, d_c, j, h_rel, 1.0, v.ct, hbuf, ctx->st));
     dse_status s = eval_residual(ctx, v.ct, v.Ft, v.St);
@@ -703,30 +678,43 @@ dse_status dse_set_physics(dse_ctx* ctx, double alpha_mu, double g0_inv, double 
   if (s != DSE_OK) return s;
   ctx->p = p;
   ctx->ph = make_phys(p);
-  // the recorded Newton step carries the physics constants as kernel
-  // arguments: record it again on the next dse_newton_step
-  if (ctx->step_exec) {
-    DeviceGuard dg(ctx->device);
-    (void)hipGraphExecDestroy(ctx->step_exec);
-    ctx->step_exec = nullptr;
-  }
+  // the recorded Newton steps carry the physics constants as kernel
+  // arguments: record them again; the held Newton matrix is the old problem's
+  DeviceGuard dg(ctx->device);
+  for (auto& g : ctx->steps)
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g = dse_ctx::StepGraph();
+    }
+  ctx->jac_at = nullptr;
   return DSE_OK;
 }
 
 namespace {
 
-// The kernels of one Newton step (J, F at c; LU; c_new = c - rho Delta;
-// F, S at c_new), enqueued on the context's stream.
+// The kernels of one Newton step: [J, F, S at c into the workspace, unless
+// they are held there already (reuse)]; LU solve J Delta = F with the update
+// c_new = c - rho Delta; J, F, S at c_new into the workspace (the matrix the
+// next step starts from); F, S copied to the caller's vectors.
 dse_status enqueue_step(dse_ctx* ctx, const double* c, double rho, double* c_new, double* F_new, double* S_new,
-                        bool capturing) {
+                        bool reuse, bool capturing) {
   const dse::Views& v = ctx->v;
   const bool timing = ctx->timing;
   if (capturing) ctx->timing = false;  // no stage events inside a recorded graph
-  dse_status s = eval_jacobian(ctx, c, v.J, v.F, v.S);
+  dse_status s = DSE_OK;
+  if (!reuse) s = eval_jacobian(ctx, c, v.J, v.F, v.S);
+  if (s == DSE_OK) {
+    const hipError_t e = dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, ctx->st, c, rho, c_new);
+    if (e != hipSuccess) {
+      set_err(ctx->err, "LU launch: %s", hipGetErrorString(e));
+      s = DSE_E_DEVICE;
+    }
+  }
+  if (s == DSE_OK) s = eval_jacobian(ctx, c_new, v.J, v.F, v.S);
   ctx->timing = timing;
   if (s != DSE_OK) return s;
-  HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, ctx->st, c, rho, c_new));  // and c_new = c - rho Delta
-  return eval_residual(ctx, c_new, F_new, S_new ? S_new : v.St);
+  HIP_TRY(ctx, dse::launch_copy2(v.n, v.F, F_new, S_new ? v.S : nullptr, S_new, ctx->st));
+  return DSE_OK;
 }
 
 }  // namespace
@@ -745,22 +733,28 @@ dse_status dse_newton_step(dse_ctx* ctx, const double* d_c, double rho, double* 
     return DSE_E_INVALID;
   }
   DeviceGuard dg(ctx->device);
+  const bool reuse = ctx->jac_at == d_c;
+  ctx->jac_at = nullptr;  // until this step is enqueued
   if (!ctx->graphs) {
-    dse_status s = enqueue_step(ctx, d_c, rho, d_c_new, d_F_new, d_S_new, false);
+    dse_status s = enqueue_step(ctx, d_c, rho, d_c_new, d_F_new, d_S_new, reuse, false);
     if (s != DSE_OK) return s;
   } else {
     const void* key[4] = {d_c, d_c_new, d_F_new, d_S_new};
-    const bool hit = ctx->step_exec && ctx->step_rho == rho && memcmp(key, ctx->step_key, sizeof key) == 0;
+    dse_ctx::StepGraph* hit = nullptr;
+    for (auto& g : ctx->steps)
+      if (g.exec && g.rho == rho && g.reuse == reuse && memcmp(key, g.key, sizeof key) == 0) hit = &g;
     if (!hit) {
-      if (ctx->step_exec) {
-        (void)hipGraphExecDestroy(ctx->step_exec);
-        ctx->step_exec = nullptr;
-      }
+      // record into the least recently used slot
+      dse_ctx::StepGraph* slot = &ctx->steps[0];
+      for (auto& g : ctx->steps)
+        if (!g.exec || (slot->exec && g.used < slot->used)) slot = &g;
+      if (slot->exec) (void)hipGraphExecDestroy(slot->exec);
+      *slot = dse_ctx::StepGraph();
       if (!ctx->cap_st) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking));
       HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal));
       const hipStream_t user_st = ctx->st;
       ctx->st = ctx->cap_st;
-      dse_status s = enqueue_step(ctx, d_c, rho, d_c_new, d_F_new, d_S_new, true);
+      dse_status s = enqueue_step(ctx, d_c, rho, d_c_new, d_F_new, d_S_new, reuse, true);
       ctx->st = user_st;
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(ctx->cap_st, &g);
@@ -769,23 +763,31 @@ dse_status dse_newton_step(dse_ctx* ctx, const double* d_c, double rho, double* 
         if (s == DSE_OK) set_err(ctx->err, "stream capture failed: %s", hipGetErrorString(ec));
         return s != DSE_OK ? s : DSE_E_DEVICE;
       }
-      const hipError_t ei = hipGraphInstantiate(&ctx->step_exec, g, nullptr, nullptr, 0);
+      const hipError_t ei = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (ei != hipSuccess) {
-        ctx->step_exec = nullptr;
+        slot->exec = nullptr;
         set_err(ctx->err, "graph instantiation failed: %s", hipGetErrorString(ei));
         return DSE_E_DEVICE;
       }
-      memcpy(ctx->step_key, key, sizeof key);
-      ctx->step_rho = rho;
+      memcpy(slot->key, key, sizeof key);
+      slot->rho = rho;
+      slot->reuse = reuse;
+      hit = slot;
     }
-    HIP_TRY(ctx, hipGraphLaunch(ctx->step_exec, ctx->st));
+    hit->used = ++ctx->step_clock;
+    HIP_TRY(ctx, hipGraphLaunch(hit->exec, ctx->st));
   }
+  ctx->jac_at = d_c_new;
   if (check) {
     int32_t flag = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
-    if (flag == DSE_E_SINGULAR) { set_err(ctx->err, "zero pivot"); return DSE_E_SINGULAR; }
+    if (flag == DSE_E_SINGULAR) {
+      ctx->jac_at = nullptr;
+      set_err(ctx->err, "zero pivot");
+      return DSE_E_SINGULAR;
+    }
   }
   return DSE_OK;
 }
@@ -810,30 +812,40 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
   const dse::Views& v = ctx->v;
   const int n = v.n;
   hipStream_t st = ctx->st;
-  double nrm[4];
-  dse_status s = eval_residual(ctx, d_c, v.F, v.S);
-  if (s == DSE_OK) s = read_norms(ctx, v.F, v.S, nullptr, nrm);
-  ++r.n_residuals;
-  double f = nrm[0];      // convergence test: max_r |F_r| / S_r
-  double f2 = nrm[3];     // line-search merit: ||F / S||_2
-  r.fnorm_hist[0] = f;
-  int it = 0, extra = 0;
-  dse_status status = s;
-  if (s == DSE_OK && !isfinite(f)) status = DSE_E_NONFINITE;
+  ctx->jac_at = nullptr;  // the workspace's J, F, S now belong to this solve
   // mixed precision: FP32 Newton matrices while they make progress, FP64 ones
   // once a step reduces the merit by less than half or it is below 1e-6 (the
   // FP32 matrix then limits the linear convergence rate)
   bool use_mix = ctx->p.precision == DSE_MIXED;
+  // J, F, S at the start: every evaluation of an accepted point is an
+  // assembly, so the next step's matrix comes with the residual that accepts it
+  double nrm[4];
+  dse_status s = eval_jacobian(ctx, d_c, v.J, v.F, v.S, use_mix ? 1 : 0);
+  if (s == DSE_OK) s = read_norms(ctx, v.F, v.S, nullptr, nrm);
+  ++r.n_jacobians;
+  if (use_mix) ++r.n_jacobians_mixed;
+  bool have_J = true;      // v.J belongs to d_c
+  bool j_mix = use_mix;    // ... in this precision
+  double f = nrm[0];       // convergence test: max_r |F_r| / S_r
+  double f2 = nrm[3];      // line-search merit: ||F / S||_2
+  r.fnorm_hist[0] = f;
+  r.fnorm2 = nrm[1];
+  int it = 0, extra = 0;
+  dse_status status = s;
+  if (s == DSE_OK && !isfinite(f)) status = DSE_E_NONFINITE;
   while (status == DSE_OK) {
     if (f < o.tol) {
       if (extra >= o.extra_iters) break;
       ++extra;
     }
     if (it >= o.max_iter) { status = DSE_E_NOCONV; break; }
-    // J and F at c (F is recomputed with J; it is the same evaluation)
-    if ((s = eval_jacobian(ctx, d_c, v.J, v.F, v.S, use_mix ? 1 : 0)) != DSE_OK) { status = s; break; }
-    ++r.n_jacobians;
-    if (use_mix) ++r.n_jacobians_mixed;
+    if (!have_J || j_mix != use_mix) {
+      // after a relaxed step, or when the precision of the matrix changes
+      if ((s = eval_jacobian(ctx, d_c, v.J, v.F, v.S, use_mix ? 1 : 0)) != DSE_OK) { status = s; break; }
+      ++r.n_jacobians;
+      if (use_mix) ++r.n_jacobians_mixed;
+      j_mix = use_mix;
+    }
     if (hipGetLastError() != hipSuccess) { status = DSE_E_DEVICE; break; }
     // the solve also writes the full step c - Delta (the update kernel's FMA)
     HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, st, d_c, 1.0, v.ct));
@@ -841,12 +853,23 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
     double rho = 1.0, ft = INFINITY, ft2 = INFINITY, dinf = 0.0;
     int32_t flag = 0;
     for (int h = 0;; ++h) {
-      if (h > 0) HIP_TRY(ctx, dse::launch_axpy(n, d_c, rho, v.dlt, v.ct, st));
-      if ((s = eval_residual(ctx, v.ct, v.Ft, v.St)) != DSE_OK) { status = s; break; }
-      ++r.n_residuals;
-      // the pivot flag arrives with the norms (one synchronisation)
-      if (h == 0) HIP_TRY(ctx, hipMemcpyAsync(&flag, v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      if ((s = read_norms(ctx, v.Ft, v.St, v.dlt, nrm)) != DSE_OK) { status = s; break; }
+      if (h == 0) {
+        // the full step in Jacobian mode: accepted, its matrix is the next one
+        if ((s = eval_jacobian(ctx, v.ct, v.J, v.F, v.S, use_mix ? 1 : 0)) != DSE_OK) { status = s; break; }
+        ++r.n_jacobians;
+        if (use_mix) ++r.n_jacobians_mixed;
+        have_J = true;
+        j_mix = use_mix;
+        // the pivot flag arrives with the norms (one synchronisation)
+        HIP_TRY(ctx, hipMemcpyAsync(&flag, v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      } else {
+        // relaxed steps in residual mode
+        HIP_TRY(ctx, dse::launch_axpy(n, d_c, rho, v.dlt, v.ct, st));
+        if ((s = eval_residual(ctx, v.ct, v.F, v.S)) != DSE_OK) { status = s; break; }
+        ++r.n_residuals;
+        have_J = false;
+      }
+      if ((s = read_norms(ctx, v.F, v.S, v.dlt, nrm)) != DSE_OK) { status = s; break; }
       if (h == 0 && flag == DSE_E_SINGULAR) { status = DSE_E_SINGULAR; set_err(ctx->err, "zero pivot"); break; }
       ft = isfinite(nrm[0]) ? nrm[0] : INFINITY;
       ft2 = isfinite(nrm[0]) && isfinite(nrm[3]) ? nrm[3] : INFINITY;
@@ -857,8 +880,6 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
     if (status != DSE_OK) break;
     if (!isfinite(ft)) { status = DSE_E_NONFINITE; break; }
     HIP_TRY(ctx, hipMemcpyAsync(d_c, v.ct, n * 8, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(ctx, hipMemcpyAsync(v.F, v.Ft, n * 8, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(ctx, hipMemcpyAsync(v.S, v.St, n * 8, hipMemcpyDeviceToDevice, st));
     if (use_mix && (ft2 > 0.5 * f2 || ft < 1e-6)) use_mix = false;
     f = ft;
     f2 = ft2;
@@ -871,9 +892,6 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
   r.iters = it;
   r.status = status;
   r.fnorm = f;
-  if (it == 0) {
-    if (read_norms(ctx, v.F, v.S, nullptr, nrm) == DSE_OK) r.fnorm2 = nrm[1];
-  }
   r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (rep) *rep = r;
   if (status == DSE_E_NOCONV) set_err(ctx->err, "no convergence after %d iterations (scaled residual %g)", it, f);

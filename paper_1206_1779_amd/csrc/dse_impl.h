@@ -100,6 +100,8 @@ struct SolveDesc {
 
 // Host helpers (dse_host.hip).
 void set_err(char* buf, const char* fmt, ...);
+// Message buffer of the calls that have no context (dse_last_error(NULL)).
+char* global_err();
 dse_status validate(const dse_params* p, char* err);
 Phys make_phys(const dse_params& p);
 size_t layout(const dse_params& p, Views* v, char* base, int ks);  // returns bytes
@@ -132,11 +134,22 @@ hipError_t launch_fd_column(int n, const double* Fp, const double* Fm, const dou
                             hipStream_t st);
 hipError_t launch_axpy(int n, const double* c, double rho, const double* d, double* out,
                        hipStream_t st);
+hipError_t launch_copy2(int n, const double* a, double* ao, const double* b /* nullable */, double* bo,
+                        hipStream_t st);
 // With cout != nullptr the solve also writes the update cout = cin - rho x.
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x,
                            int trans, hipStream_t st, const double* cin = nullptr, double rho = 0.0,
                            double* cout = nullptr);
 void lu_setup();  // LDS attributes of the factorisation kernels (call before any capture)
+
+// Observables (dse_observables.hip).  launch_gl: n-node Gauss-Legendre rule
+// into x, w; tab holds 16 (n - 1) bytes of recurrence coefficients.
+hipError_t launch_gl(int n, double* x, double* w, void* tab, hipStream_t st);
+int schwinger_chunks(int n);  // partial sums per time of the Schwinger sum
+hipError_t launch_schwinger(const Views& v, const Phys& ph, const double* c, int n, double p_max, const double* x,
+                            const double* w, const double* t, int m, double* out, double* pn, double* gn,
+                            double* part, hipStream_t st);
+hipError_t launch_renorm(const Views& v, const Phys& ph, const double* c, int scan, double* out, hipStream_t st);
 
 // Batched family (one launch per stage for all problems whose mask entry is
 // set).  `which` selects the evaluation point and outputs: 0 = the packed
@@ -166,3 +179,45 @@ hipError_t launch_batch_accept(const BatchArgs& a, double* cpk, hipStream_t st);
 hipError_t launch_batch_pack(const BatchArgs& a, double* Jpk, double* Fpk, hipStream_t st);
 
 }  // namespace dse
+
+// The context behind the opaque dse_ctx handle of the C ABI.
+struct dse_ctx {
+  dse_params p;
+  dse::Views v;
+  dse::Phys ph;
+  hipStream_t st;
+  int device;
+  char* ws;
+  size_t ws_bytes;
+  bool timing;
+  // event ring: per timed dse_jacobian, events before dressing, before the
+  // gluon point kernel, between gluon and ghost, after ghost, after the
+  // contraction, after the assembly
+  static constexpr int kRing = 64;
+  static constexpr int kEv = 6;
+  hipEvent_t ev[kRing][kEv];
+  int ring_count;
+  double acc_ms[5];
+  int acc_n;
+  // Newton matrix, residual and scale held in the workspace (v.J, v.F, v.S)
+  // for the coefficients at this device pointer (nullptr: nothing held)
+  const double* jac_at = nullptr;
+  // recorded Newton steps (dse_newton_step): the launch sequence for one set
+  // of pointers, relaxation and kind (with or without the assembly at d_c),
+  // replayed as a HIP graph; a few are kept (alternating buffers need two)
+  bool graphs = true;
+  hipStream_t cap_st = nullptr;  // private stream the graphs are recorded on (the
+                                 // caller's stream may be the null stream, which
+                                 // cannot be captured); replays go to st
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
+    double rho = 0.0;
+    bool reuse = false;
+    unsigned long long used = 0;
+  };
+  static constexpr int kSteps = 4;
+  StepGraph steps[kSteps];
+  unsigned long long step_clock = 0;
+  char err[512];
+};

@@ -896,6 +896,16 @@ __global__ void axpy_kernel(int n, const double* c, double rho, const double* d,
   if (i < n) out[i] = fma(-rho, d[i], c[i]);
 }
 
+// ao = a and (when bo != nullptr) bo = b, n entries each.
+__global__ void copy2_kernel(int n, const double* __restrict__ a, double* __restrict__ ao,
+                             const double* __restrict__ b, double* __restrict__ bo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    ao[i] = a[i];
+    if (bo) bo[i] = b[i];
+  }
+}
+
 // --------------------------------------------------------------------------
 // FP64 LU with partial pivoting and the triangular solves, one workgroup of
 // four waves; the padded matrix [A | b] lives in LDS (or in global memory
@@ -1824,6 +1834,11 @@ hipError_t launch_fd_shift(int n, const double* c, int j, double h_rel, double s
 hipError_t launch_fd_column(int n, const double* Fp, const double* Fm, const double* hbuf, int j, double* J,
                             hipStream_t st) {
   hipLaunchKernelGGL(fd_column_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Fp, Fm, hbuf, j, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2(int n, const double* a, double* ao, const double* b, double* bo, hipStream_t st) {
+  hipLaunchKernelGGL(copy2_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, a, ao, b, bo);
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ EXPORTS = [
     "dse_batch_workspace_bytes", "dse_batch_init", "dse_batch_destroy", "dse_batch_last_error",
     "dse_batch_offsets", "dse_batch_start_guess", "dse_batch_jacobian", "dse_batch_newton_solve",
     "dse_batch_autotune", "dse_batch_set_launch", "dse_batch_get_launch",
+    "dse_renorm_scale", "dse_gauss_legendre_workspace_bytes", "dse_gauss_legendre",
+    "dse_schwinger_workspace_bytes", "dse_schwinger",
 ]
 
 
@@ -95,6 +97,11 @@ def load():
             "dse_dressing_vjp": (C.c_int, [vp, vp, C.c_int32, vp, vp, vp]),
             "dse_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
             "dse_lu_solve": (C.c_int, [vp, vp, vp, vp, C.c_int32]),
+            "dse_renorm_scale": (C.c_int, [vp, vp, vp]),
+            "dse_gauss_legendre_workspace_bytes": (C.c_size_t, [C.c_int32]),
+            "dse_gauss_legendre": (C.c_int, [C.c_int32, vp, vp, vp, C.c_size_t, vp]),
+            "dse_schwinger_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+            "dse_schwinger": (C.c_int, [vp, vp, C.c_int32, C.c_double, vp, C.c_int32, vp, vp, C.c_size_t]),
             "dse_status_string": (C.c_char_p, [C.c_int]),
             "dse_last_error": (C.c_char_p, [vp]),
             "dse_sizes": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -140,6 +147,28 @@ def params(**kw) -> Params:
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def gauss_legendre(n: int, device="cuda", stream: torch.cuda.Stream | None = None):
+    """dse_gauss_legendre: the n-node Gauss-Legendre rule (nodes ascending,
+    weights) computed on the device; returns two float64 tensors."""
+    lib = load()
+    dev = torch.device(device)
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    nb = lib.dse_gauss_legendre_workspace_bytes(int(n))
+    if nb == 0:
+        raise DSEError(1, "n = %d out of range" % n)
+    with torch.cuda.device(dev):
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        x = torch.empty(n, dtype=torch.float64, device=dev)
+        w = torch.empty(n, dtype=torch.float64, device=dev)
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        wp = (ws.data_ptr() + 255) // 256 * 256
+        s = lib.dse_gauss_legendre(int(n), _ptr(x), _ptr(w), C.c_void_p(wp), nb, C.c_void_p(st.cuda_stream))
+    if s:
+        raise DSEError(s, lib.dse_last_error(None).decode())
+    return x, w
 
 
 @dataclass
@@ -274,6 +303,33 @@ class Solver:
         with torch.cuda.device(self.device):
             self._check(self.lib.dse_dressing_vjp(self.h, _ptr(u), m, _ptr(wZ), _ptr(wG), _ptr(g)))
         return g
+
+    def renorm_scale(self, c) -> float:
+        """mu^2 with G^2(mu^2) Z(mu^2) = 1 (dse_renorm_scale); NaN if none."""
+        c = self._vec(c)
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_renorm_scale(self.h, _ptr(c), _ptr(out)))
+        return float(out.item())
+
+    def schwinger(self, c, t, n: int = 1 << 17, p_max: float = 1e3, ws: torch.Tensor | None = None):
+        """Delta(t) of the gluon propagator (dse_schwinger) with the n-node
+        mapped rule on [0, p_max]; `ws` (uint8 device tensor, optional) is the
+        workspace, reused across calls when given."""
+        c = self._vec(c)
+        t = torch.as_tensor(t, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+        m = int(t.numel())
+        nb = self.lib.dse_schwinger_workspace_bytes(int(n), m)
+        if nb == 0:
+            raise DSEError(1, "n = %d or m = %d out of range" % (n, m))
+        if ws is None or ws.numel() < nb + 256:
+            ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        wp = (ws.data_ptr() + 255) // 256 * 256
+        out = torch.empty(m, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            self._check(self.lib.dse_schwinger(self.h, _ptr(c), int(n), float(p_max), _ptr(t), m, _ptr(out),
+                                               C.c_void_p(wp), nb))
+        return out
 
     def lu_solve(self, J, b, trans: bool = False) -> torch.Tensor:
         J = torch.as_tensor(J, dtype=torch.float64).to(self.device).contiguous()
