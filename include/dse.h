@@ -258,6 +258,25 @@ dse_status dse_set_graphs(dse_ctx* ctx, int32_t on);
 dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, double* d_x,
                         int32_t trans);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): the solve of dse_lu_solve
+ * without a context or workspace.  Solves J x = b (trans = 0) or J^T x = b
+ * (trans != 0) for a row-major n x n d_J, 1 <= n <= 2 * DSE_MAX_N, with the
+ * same device LU (partial pivoting; results identical to dse_lu_solve).  d_J,
+ * d_b (length n) are not modified; d_x (length n) may equal d_b.  d_info
+ * (device int32, nullable) receives 0 or DSE_E_SINGULAR (zero or non-finite
+ * pivot; d_x is then undefined).  Enqueued on hip_stream (a hipStream_t; NULL
+ * = default stream) of the current device without synchronising; allocates
+ * nothing.  Scratch: one static device array of 528 KiB per GPU (the padded
+ * factors when they do not fit in LDS, the pivot rows, the status word when
+ * d_info is NULL), taken by the first call on that GPU and kept until the
+ * process ends.  Every call on a GPU shares that array: calls that overlap on
+ * one GPU (several streams or threads at once) race.  Invalid n or NULL
+ * d_J / d_b / d_x: DSE_E_INVALID before any launch, message in
+ * dse_last_error(NULL). */
+dse_status dse_lu_solve_noalloc(int32_t n, const double* d_J, const double* d_b, double* d_x, int32_t trans,
+                                int32_t* d_info, void* hip_stream);
+
 /* Vector-Jacobian products at c for a weight vector u (length n):
  *   d_uJ[k]     = sum_r u_r dF_r/dc_k                     (n entries; nullable)
  *   d_utheta[0] = sum_r u_r dF_r/d alpha_mu                (3 entries; nullable)

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdse.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("dse_host.hip", "dse_kernels.hip", "dse_batch.hip",
-                                                    "dse_observables.hip")]
+                                                    "dse_noalloc.hip", "dse_observables.hip")]
 
 # Packed FP32 instructions are switched off for all device code.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

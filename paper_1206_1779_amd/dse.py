@@ -29,7 +29,7 @@ EXPORTS = [
     "dse_set_physics", "dse_newton_step", "dse_set_graphs",
     "dse_batch_workspace_bytes", "dse_batch_init", "dse_batch_destroy", "dse_batch_last_error",
     "dse_batch_offsets", "dse_batch_start_guess", "dse_batch_jacobian", "dse_batch_newton_solve",
-    "dse_batch_autotune", "dse_batch_set_launch", "dse_batch_get_launch",
+    "dse_batch_autotune", "dse_batch_set_launch", "dse_batch_get_launch", "dse_lu_solve_noalloc",
     "dse_renorm_scale", "dse_gauss_legendre_workspace_bytes", "dse_gauss_legendre",
     "dse_schwinger_workspace_bytes", "dse_schwinger",
 ]
@@ -97,6 +97,7 @@ def load():
             "dse_dressing_vjp": (C.c_int, [vp, vp, C.c_int32, vp, vp, vp]),
             "dse_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
             "dse_lu_solve": (C.c_int, [vp, vp, vp, vp, C.c_int32]),
+            "dse_lu_solve_noalloc": (C.c_int, [C.c_int32, vp, vp, vp, C.c_int32, vp, vp]),
             "dse_renorm_scale": (C.c_int, [vp, vp, vp]),
             "dse_gauss_legendre_workspace_bytes": (C.c_size_t, [C.c_int32]),
             "dse_gauss_legendre": (C.c_int, [C.c_int32, vp, vp, vp, C.c_size_t, vp]),
@@ -147,6 +148,29 @@ def params(**kw) -> Params:
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def lu_solve_noalloc(J: torch.Tensor, b: torch.Tensor, x: torch.Tensor, trans: bool = False,
+                     info: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None) -> None:
+    """dse_lu_solve_noalloc: x = J^{-1} b (or J^{-T} b) into the caller's x,
+    enqueued on `stream` (default: the current stream of x's device) without
+    any allocation; `info` (int32 device scalar, optional) receives the pivot
+    status.  All tensors float64, contiguous, on one device."""
+    lib = load()
+    n = int(b.numel())
+    for t in (J, b, x):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("J, b and x must be contiguous float64 device tensors")
+    if J.shape != (n, n) or x.numel() != n:
+        raise ValueError("J must be n x n for vectors of length n")
+    if info is not None and (info.dtype != torch.int32 or info.device != x.device):
+        raise ValueError("info must be an int32 tensor on the same device")
+    with torch.cuda.device(x.device):
+        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        s = lib.dse_lu_solve_noalloc(n, _ptr(J), _ptr(b), _ptr(x), 1 if trans else 0, _ptr(info),
+                                     C.c_void_p(st.cuda_stream))
+    if s:
+        raise DSEError(s, lib.dse_last_error(None).decode())
 
 
 def gauss_legendre(n: int, device="cuda", stream: torch.cuda.Stream | None = None):
