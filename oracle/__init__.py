@@ -41,7 +41,7 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [
         ("n_z", C.c_int32), ("n_g", C.c_int32), ("n_rad", C.c_int32),
-        ("n_ir", C.c_int32), ("n_ang", C.c_int32), ("pad_", C.c_int32),
+        ("n_ir", C.c_int32), ("n_ang", C.c_int32), ("quad", C.c_int32),
         ("eps2", C.c_double), ("lambda2", C.c_double), ("ir_efolds", C.c_double),
         ("alpha_mu", C.c_double), ("n_c", C.c_double), ("g0_inv", C.c_double),
         ("z_lambda_inv", C.c_double), ("kappa", C.c_double), ("delta", C.c_double),
@@ -88,6 +88,7 @@ def load():
             "dse_ref_momentum_z": (C.c_double, [C.c_double] * 3),
             "dse_ref_grid_sizes": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "dse_ref_grid": (C.c_int, [P, _D, _D, _D, _D, _D, _D]),
+            "dse_ref_row_grid": (C.c_int, [P, C.c_double, _D, _D]),
             "dse_ref_pi_gluon": (C.c_double, [P, _D, C.c_double, C.c_int, _D, _D, C.c_int, _D, _D]),
             "dse_ref_pi_ghost": (C.c_double, [P, _D, C.c_double, C.c_int, _D, _D, C.c_int, _D, _D]),
             "dse_ref_residual": (C.c_int, [P, _D, _D]),
@@ -119,7 +120,11 @@ KAPPA = (93.0 - 1201.0 ** 0.5) / 98.0
 DELTA = -9.0 / 44.0   # Sec. 2, ghost anomalous dimension
 GAMMA = -13.0 / 22.0  # Sec. 2, gluon anomalous dimension
 
-_DEFAULTS = dict(n_z=16, n_g=16, n_rad=64, n_ir=16, n_ang=16, eps2=1e-6, lambda2=1e6,
+#: quadrature bits: tanh-sinh angular rule, radial split at x (Sec. 2, Sec. 3)
+QUAD_TANH_SINH = 1
+QUAD_SPLIT = 2
+
+_DEFAULTS = dict(n_z=16, n_g=16, n_rad=64, n_ir=16, n_ang=16, quad=0, eps2=1e-6, lambda2=1e6,
                  ir_efolds=40.0, alpha_mu=1.0, n_c=3.0, g0_inv=0.0, z_lambda_inv=1.0,
                  kappa=KAPPA, delta=DELTA, gamma=GAMMA)
 
@@ -259,6 +264,16 @@ def grid(p: Params) -> Grid:
     if st:
         raise ValueError("invalid parameters")
     return g
+
+
+def row_grid(p: Params, x: float):
+    """Radial nodes and weights of the row at x with the split at x (Sec. 3)."""
+    m = p.n_ir + 2 * p.n_rad
+    y = np.zeros(m); W = np.zeros(m)
+    k = load().dse_ref_row_grid(C.byref(p), float(x), y.ctypes.data_as(_D), W.ctypes.data_as(_D))
+    if k < 0:
+        raise ValueError("invalid parameters")
+    return y[:k], W[:k]
 
 
 def pi_gluon(p: Params, c, x, y, W, theta, v) -> float:

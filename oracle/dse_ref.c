@@ -255,6 +255,9 @@ int dse_ref_grid_sizes(const dse_ref_params* p, int32_t* nq, int32_t* nk) {
 
 static int check_params(const dse_ref_params* p) {
   if (p->n_z < 1 || p->n_g < 1 || p->n_z > 1024 || p->n_g > 1024) return 1;
+  if (p->quad & ~3) return 1;
+  /* the tanh-sinh rule is symmetric about xi = 0: 2K + 1 nodes, K >= 1 */
+  if ((p->quad & 1) && (p->n_ang < 3 || p->n_ang % 2 == 0)) return 1;
   /* the grid builder's Gauss-Legendre scratch holds GL_MAX nodes per rule */
   if (p->n_rad < 1 || p->n_ir < 0 || p->n_ang < 1) return 1;
   if (p->n_rad > GL_MAX || p->n_ir > GL_MAX || p->n_ang > GL_MAX) return 1;
@@ -262,6 +265,83 @@ static int check_params(const dse_ref_params* p) {
   if (!(p->alpha_mu > 0.0) || !(p->n_c > 0.0)) return 1;
   if (p->n_ir > 0 && !(p->ir_efolds > 0.0)) return 1;
   return 0;
+}
+
+/* Tanh-sinh (double exponential) rule of Takahasi and Mori in xi = cos(theta)
+ * on (-1, 1), the angular rule of Sec. 2: xi_k = tanh(u_k), u_k = (pi/2)
+ * sinh(k h), weight h (pi/2) cosh(k h) / cosh(u_k)^2, k = -K .. K, n_ang =
+ * 2K + 1, truncated at |k h| = 3 (there 1 - |xi| = 4e-14 and the weight is
+ * 1e-12 of the central one): h = 3/K.  The
+ * nodes go to the caller as angles, theta = 2 atan(sqrt((1 - xi)/(1 + xi)))
+ * with 1 - xi = 2/(1 + e^{2u}) and 1 + xi = 2/(1 + e^{-2u}) (no cancellation
+ * next to the ends), and d-theta weights v = w_xi / sin(theta): then
+ * sum_k v_k sin^2(theta_k) f = sum_k w_k sqrt(1 - xi_k^2) f, the measure of
+ * Sec. 2, and sum_k v_k sin^4(theta_k) f is the ghost's (1 - xi^2)^{3/2}.
+ * Otherwise: Gauss-Legendre in theta on (0, pi). */
+#define TS_TMAX 3.0
+static void angular_rule(const dse_ref_params* p, double* theta, double* v) {
+  if (p->quad & 1) {
+    const int K = (p->n_ang - 1) / 2;
+    const double h = TS_TMAX / K;
+    for (int k = -K; k <= K; ++k) {
+      double uk = 0.5 * REF_PI * sinh(k * h);
+      double om = 2.0 / (1.0 + exp(2.0 * uk));   /* 1 - xi */
+      double op = 2.0 / (1.0 + exp(-2.0 * uk));  /* 1 + xi */
+      double ch = cosh(uk);
+      double w = h * 0.5 * REF_PI * cosh(k * h) / (ch * ch);
+      double th = 2.0 * atan(sqrt(om / op));
+      theta[k + K] = th;
+      v[k + K] = w / sqrt(om * op);
+    }
+    return;
+  }
+  double* u = (double*)malloc(sizeof(double) * p->n_ang);
+  double* wu = (double*)malloc(sizeof(double) * p->n_ang);
+  dse_ref_gauss_legendre(p->n_ang, u, wu);
+  for (int k = 0; k < p->n_ang; ++k) {
+    theta[k] = 0.5 * REF_PI * (1.0 + u[k]);
+    v[k] = 0.5 * REF_PI * wu[k];
+  }
+  free(u);
+  free(wu);
+}
+
+/* Gauss-Legendre in ln y on [ln a, ln b] (n nodes, starting at y[0]): the
+ * integral over y of f is the integral over t = ln y of y f(y). */
+static void log_gl(int n, double a, double b, const double* u, const double* wu, double* y, double* W) {
+  for (int i = 0; i < n; ++i) {
+    double t = 0.5 * (a + b) + 0.5 * (b - a) * u[i];
+    y[i] = exp(t);
+    W[i] = 0.5 * (b - a) * wu[i] * y[i];
+  }
+}
+
+int dse_ref_row_grid(const dse_ref_params* p, double x, double* y, double* W) {
+  if (check_params(p)) return -1;
+  double lo = log(p->eps2), hi = log(p->lambda2);
+  double* u = (double*)malloc(sizeof(double) * GL_MAX);
+  double* wu = (double*)malloc(sizeof(double) * GL_MAX);
+  int q = 0;
+  if (p->n_ir > 0) {
+    dse_ref_gauss_legendre(p->n_ir, u, wu);
+    log_gl(p->n_ir, lo - p->ir_efolds, lo, u, wu, y, W);
+    q = p->n_ir;
+  }
+  dse_ref_gauss_legendre(p->n_rad, u, wu);
+  if (x > p->eps2 && x < p->lambda2) {
+    log_gl(p->n_rad, lo, log(x), u, wu, y + q, W + q);
+    q += p->n_rad;
+    log_gl(p->n_rad, log(x), hi, u, wu, y + q, W + q);
+    q += p->n_rad;
+  } else {
+    log_gl(p->n_rad, lo, hi, u, wu, y + q, W + q);
+    q += p->n_rad;
+  }
+  if (g_jitter != 0.0)
+    for (int i = 0; i < q; ++i) W[i] *= 1.0 + ((i * 7919 % 13) % 2 ? g_jitter : -g_jitter);
+  free(u);
+  free(wu);
+  return q;
 }
 
 /* Radial: Gauss-Legendre in t = ln y on [ln eps2, ln lambda2] (n_rad nodes)
@@ -290,11 +370,7 @@ int dse_ref_grid(const dse_ref_params* p, double* y, double* W, double* theta, d
     y[q] = exp(t);
     W[q] = 0.5 * (hi - lo) * wu[i] * y[q];
   }
-  dse_ref_gauss_legendre(p->n_ang, u, wu);
-  for (int k = 0; k < p->n_ang; ++k) {
-    theta[k] = 0.5 * REF_PI * (1.0 + u[k]);
-    v[k] = 0.5 * REF_PI * wu[k];
-  }
+  angular_rule(p, theta, v);
   /* rounding-floor probe: scale every weight by 1 +- g_jitter (0 by default) */
   if (g_jitter != 0.0) {
     for (int i = 0; i < p->n_ir + p->n_rad; ++i) W[i] *= 1.0 + ((i * 7919 % 13) % 2 ? g_jitter : -g_jitter);
@@ -459,7 +535,17 @@ static void eval_rows(const dse_ref_params* p, const double* c, const grid_t* g,
     if (r < n && need && !need[r]) continue;
     double x; int kind;
     row_point(p, g, r, &x, &kind);
-    row_eval(p, c, x, g->nq, g->y, g->W, g->nk, g->th, g->v, kind, &rr[r]);
+    if (p->quad & 2) {
+      /* the row's own radial grid, split at x (Sec. 3) */
+      double* y = (double*)malloc(sizeof(double) * (p->n_ir + 2 * p->n_rad));
+      double* W = (double*)malloc(sizeof(double) * (p->n_ir + 2 * p->n_rad));
+      int nq = dse_ref_row_grid(p, x, y, W);
+      row_eval(p, c, x, nq, y, W, g->nk, g->th, g->v, kind, &rr[r]);
+      free(y);
+      free(W);
+    } else {
+      row_eval(p, c, x, g->nq, g->y, g->W, g->nk, g->th, g->v, kind, &rr[r]);
+    }
   }
 }
 

@@ -35,8 +35,12 @@ typedef struct {
   int32_t n_g;          /* Chebyshev coefficients of ln G (vector b)            */
   int32_t n_rad;        /* Gauss-Legendre nodes in ln y on [eps2, lambda2]      */
   int32_t n_ir;         /* Gauss-Legendre nodes in ln y on the IR panel         */
-  int32_t n_ang;        /* Gauss-Legendre nodes in theta on (0, pi)             */
-  int32_t pad_;
+  int32_t n_ang;        /* angular nodes                                        */
+  int32_t quad;         /* quadrature rules, bits: 1 = tanh-sinh rule in
+                           xi = cos(theta) for the angle (Sec. 2), 2 = radial
+                           integral split at the external momentum x (Sec. 3);
+                           0 = Gauss-Legendre in theta and one log-GL radial
+                           grid shared by all rows                            */
   double eps2;          /* IR matching point epsilon^2 (lower end of mapping)  */
   double lambda2;       /* UV cutoff Lambda^2 (upper end of mapping)           */
   double ir_efolds;     /* IR panel covers [eps2*exp(-ir_efolds), eps2]        */
@@ -96,10 +100,18 @@ double dse_ref_kernel_M_printed(double x, double y, double z);
 double dse_ref_kernel_M(double x, double y, double theta);
 double dse_ref_momentum_z(double x, double y, double theta);
 
-/* Quadrature grid of the discretised problem. */
+/* Quadrature grid of the discretised problem: the shared radial grid (IR
+ * panel, then n_rad log-GL nodes on [eps2, lambda2]), the angular rule as
+ * theta nodes with d-theta weights v, and the external points. */
 int dse_ref_grid_sizes(const dse_ref_params* p, int32_t* nq, int32_t* nk);
 int dse_ref_grid(const dse_ref_params* p, double* y, double* W, double* theta, double* v,
                  double* x_z, double* x_g);
+/* Radial grid of the row at external momentum x with the split of Sec. 3
+ * (quad bit 2): the IR panel, then n_rad log-GL nodes on [eps2, x] and n_rad
+ * on [x, lambda2]; for x outside (eps2, lambda2) the one interval
+ * [eps2, lambda2].  y and W hold n_ir + 2 n_rad entries; returns the number
+ * of nodes, or -1 for invalid parameters. */
+int dse_ref_row_grid(const dse_ref_params* p, double x, double* y, double* W);
 
 /* Self-energies Pi_Z(x), Pi_G(x) (Sec. 2) on an arbitrary radial grid
  * (y[q], W[q]: integral over y = sum_q W[q] f(y[q])) and angular grid
