@@ -66,6 +66,19 @@ typedef enum {
  * residual either way. */
 typedef enum { DSE_FP64 = 0, DSE_MIXED = 1 } dse_precision;
 
+/* Quadrature rules of the paper (dse_params.quad, bits):
+ * DSE_QUAD_TANH_SINH: the angular integral by the tanh-sinh rule in
+ *   xi = cos(theta) (Sec. 2): xi_k = tanh((pi/2) sinh(k h)), k = -K .. K,
+ *   n_ang = 2K + 1 (odd, >= 3), h = 3/K;
+ * DSE_QUAD_SPLIT: the radial integral split at each row's external momentum,
+ *   [0, eps2] + [eps2, x] + [x, lambda2] (Sec. 3), n_rad log-GL nodes on each
+ *   interval above eps2 and the IR panel below (rows at x = 0 and
+ *   x = lambda2: the one interval [eps2, lambda2]).  Every row then has its
+ *   own grid, and the q-side derivative sums are accumulated per row in the
+ *   point kernels (no B.T product).  FP64 only: with DSE_MIXED, in a batched
+ *   family, or for dse_vjp it is rejected (DSE_E_INVALID). */
+enum { DSE_QUAD_TANH_SINH = 1, DSE_QUAD_SPLIT = 2 };
+
 typedef struct dse_ctx dse_ctx; /* opaque */
 
 /* Problem definition (Sec. 2-3).  dse_params_default() fills the paper's
@@ -79,9 +92,12 @@ typedef struct {
   int32_t n_ir;          /* Gauss-Legendre nodes in ln y on the IR panel
                             [eps2 exp(-ir_efolds), eps2] (stands for the
                             integral from 0 to eps2 of the radial split, Sec. 3) */
-  int32_t n_ang;         /* Gauss-Legendre nodes in theta on (0, pi)            */
+  int32_t n_ang;         /* angular nodes                                        */
   int32_t precision;     /* dse_precision                                        */
-  int32_t reserved_;
+  int32_t quad;          /* quadrature rules (dse_quadrature bits); 0: one
+                            radial grid shared by all rows (Gauss-Legendre in
+                            ln y on [eps2, lambda2] with n_rad nodes, plus the
+                            IR panel) and Gauss-Legendre in theta               */
   double eps2, lambda2;  /* interval [epsilon^2, Lambda^2] of the expansion      */
   double ir_efolds;      /* length of the IR panel in ln y                       */
   double alpha_mu;       /* alpha(mu^2) = g^2/(4 pi)                              */

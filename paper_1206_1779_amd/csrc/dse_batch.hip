@@ -207,7 +207,7 @@ size_t dse_batch_workspace_bytes(const dse_params* p, int32_t count) {
   char tmp[512];
   int cap = kSlicesCap;
   for (int b = 0; b < count; ++b) {
-    if (dse::validate(&p[b], tmp) != DSE_OK) return 0;
+    if (dse::validate(&p[b], tmp) != DSE_OK || (p[b].quad & DSE_QUAD_SPLIT)) return 0;
     cap = std::min(cap, slices_cap(p[b]));
   }
   const Sizes s = sizes(p, count, cap);
@@ -228,6 +228,10 @@ dse_status dse_batch_init(const dse_params* p, int32_t count, void* d_workspace,
     }
     if (p[b].precision != DSE_FP64) {
       set_err(g_batch_err, "problem %d: the batched family runs in FP64 (precision must be DSE_FP64)", b);
+      return DSE_E_INVALID;
+    }
+    if (p[b].quad & DSE_QUAD_SPLIT) {
+      set_err(g_batch_err, "problem %d: the batched family shares one radial grid per problem (no DSE_QUAD_SPLIT)", b);
       return DSE_E_INVALID;
     }
     cap = std::min(cap, slices_cap(p[b]));

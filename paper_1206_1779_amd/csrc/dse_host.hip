@@ -145,6 +145,18 @@ dse_status validate(const dse_params* p, char* err) {
     set_err(err, "precision %d unknown", p->precision);
     return DSE_E_INVALID;
   }
+  if (p->quad & ~(DSE_QUAD_TANH_SINH | DSE_QUAD_SPLIT)) {
+    set_err(err, "quad = %d: unknown quadrature bits", p->quad);
+    return DSE_E_INVALID;
+  }
+  if ((p->quad & DSE_QUAD_TANH_SINH) && (p->n_ang < 3 || p->n_ang % 2 == 0)) {
+    set_err(err, "the tanh-sinh rule needs an odd n_ang >= 3 (got %d)", p->n_ang);
+    return DSE_E_INVALID;
+  }
+  if ((p->quad & DSE_QUAD_SPLIT) && p->precision != DSE_FP64) {
+    set_err(err, "the split radial grid runs in FP64 only");
+    return DSE_E_INVALID;
+  }
   return DSE_OK;
 }
 
@@ -177,7 +189,8 @@ size_t layout(const dse_params& p, Views* v, char* base, int ks) {
   t.n_g = p.n_g;
   t.n = p.n_z + p.n_g;
   t.NJ = padded_order(p.n_z > p.n_g ? p.n_z : p.n_g);
-  t.Q = p.n_rad + p.n_ir;
+  t.split = (p.quad & DSE_QUAD_SPLIT) ? 1 : 0;
+  t.Q = (t.split ? 2 * p.n_rad : p.n_rad) + p.n_ir;  // nodes per row
   t.Qp = pad_up(t.Q, kQPad);
   t.K = p.n_ang;
   t.Kp = pad_up(t.K, kKPad);
@@ -218,8 +231,14 @@ size_t layout(const dse_params& p, Views* v, char* base, int ks) {
   t.xrow = (double*)take((t.RZ + t.RG) * d);
   t.lnX = (double*)take(t.n * d);
   t.ang = (double*)take(5 * t.Kp * d);
+  const size_t nr = t.split ? (size_t)(t.RZ + t.RG) * t.Qp : 0;
+  t.yr = t.split ? (double*)take(nr * d) : nullptr;
+  t.Wr = t.split ? (double*)take(nr * d) : nullptr;
+  t.syr = t.split ? (double*)take(nr * d) : nullptr;
+  t.lnZyr = t.split ? (double*)take(nr * d) : nullptr;
+  t.lnGyr = t.split ? (double*)take(nr * d) : nullptr;
   t.Bm = (double*)take((size_t)t.KS * t.Rbp * t.Qp * d);
-  t.Dp = (double*)take((size_t)(2 * t.RZ + t.RG) * t.nqt * t.KS * t.NJ * d);
+  t.Dp = (double*)take((size_t)(2 * t.RZ + t.RG + (t.split ? t.RG : 0)) * t.nqt * t.KS * t.NJ * d);
   t.Pip = (double*)take((size_t)2 * (t.RZ + t.RG) * t.nqt * t.KS * d);
   t.Absp = (double*)take((size_t)(t.RZ + t.RG) * t.nqt * t.KS * d);
   t.Eq = (double*)take((size_t)dse::kCS * t.Rbp * t.NJ * d);
@@ -289,9 +308,32 @@ dse_status upload_tables(const dse_params& p, const Views& v, const Phys& ph, hi
   xrow[v.RZ + v.RG - 1] = 0.0;        // ghost subtraction point x_G = 0
 
   std::vector<double> ang(5 * (size_t)v.Kp, 0.0);
-  gauss_legendre(p.n_ang, u, wu);
-  for (int k = 0; k < v.Kp; ++k) {
-    if (k < p.n_ang) {
+  for (int k = p.n_ang; k < v.Kp; ++k) ang[v.Kp + k] = 0.5;  // padding angles: zero weight
+  if (p.quad & DSE_QUAD_TANH_SINH) {
+    // tanh-sinh in xi = cos(theta) (Sec. 2): int dtheta sin^2 f = int dxi
+    // sqrt(1 - xi^2) f; xi_k = tanh(u_k), u_k = (pi/2) sinh(k h), weight
+    // h (pi/2) cosh(k h) / cosh^2(u_k), k = -K .. K, h = 3 / K.  1 - xi and
+    // 1 + xi come from e^{+-2u} (no cancellation next to the ends), so
+    // sin^2(theta/2) = (1 - xi)/2 and sin^2(theta) = (1 - xi)(1 + xi).
+    const int K = (p.n_ang - 1) / 2;
+    const double h = 3.0 / K;
+    for (int k = -K; k <= K; ++k) {
+      const int i = k + K;
+      const double uk = 0.5 * kPi * sinh(k * h);
+      const double om = 2.0 / (1.0 + exp(2.0 * uk));
+      const double op = 2.0 / (1.0 + exp(-2.0 * uk));
+      const double ch = cosh(uk);
+      const double w = h * 0.5 * kPi * cosh(k * h) / (ch * ch);
+      const double s2 = om * op, sn = sqrt(s2);
+      ang[i] = tanh(uk);
+      ang[v.Kp + i] = 0.5 * om;
+      ang[2 * v.Kp + i] = w * sn;
+      ang[3 * v.Kp + i] = w * s2 * sn;
+      ang[4 * v.Kp + i] = s2;
+    }
+  } else {
+    gauss_legendre(p.n_ang, u, wu);
+    for (int k = 0; k < p.n_ang; ++k) {
       const double th = 0.5 * kPi * (1.0 + u[k]);
       const double vk = 0.5 * kPi * wu[k];
       const double sn = sin(th), sh = sin(0.5 * th);
@@ -300,8 +342,43 @@ dse_status upload_tables(const dse_params& p, const Views& v, const Phys& ph, hi
       ang[2 * v.Kp + k] = vk * sn * sn;
       ang[3 * v.Kp + k] = vk * sn * sn * sn * sn;
       ang[4 * v.Kp + k] = sn * sn;
-    } else {
-      ang[v.Kp + k] = 0.5;  // padding angle: zero weight
+    }
+  }
+  // split radial grids (Sec. 3): per row the IR panel, then n_rad log-GL
+  // nodes on [eps2, x] and on [x, lambda2] (rows at x = 0 or lambda2: n_rad on
+  // [eps2, lambda2]); s(y) from ln y directly
+  const size_t nr = v.split ? (size_t)(v.RZ + v.RG) * v.Qp : 0;
+  std::vector<double> yr(nr, 1.0), Wr(nr, 0.0), syr(nr, 0.0);
+  if (v.split) {
+    std::vector<double> gi, gwi, gr, gwr;
+    if (p.n_ir > 0) gauss_legendre(p.n_ir, gi, gwi);
+    gauss_legendre(p.n_rad, gr, gwr);
+    auto panel = [&](const std::vector<double>& g, const std::vector<double>& gw, double a, double b,
+                     double* yo, double* Wo, double* so) {
+      for (size_t i = 0; i < g.size(); ++i) {
+        const double tq = 0.5 * (a + b) + 0.5 * (b - a) * g[i];
+        yo[i] = exp(tq);
+        Wo[i] = 0.5 * (b - a) * gw[i] * yo[i];
+        so[i] = std::min(1.0, std::max(-1.0, (tq - ph.L0) * ph.invL1));
+      }
+    };
+    for (int r = 0; r < v.RZ + v.RG; ++r) {
+      double* yo = &yr[(size_t)r * v.Qp];
+      double* Wo = &Wr[(size_t)r * v.Qp];
+      double* so = &syr[(size_t)r * v.Qp];
+      int off = 0;
+      if (p.n_ir > 0) {
+        panel(gi, gwi, ph.ln_eps2 - p.ir_efolds, ph.ln_eps2, yo, Wo, so);
+        off = p.n_ir;
+      }
+      const double xr = xrow[r];
+      if (xr > p.eps2 && xr < p.lambda2) {
+        const double lx = log(xr);
+        panel(gr, gwr, ph.ln_eps2, lx, yo + off, Wo + off, so + off);
+        panel(gr, gwr, lx, ph.ln_lam2, yo + off + p.n_rad, Wo + off + p.n_rad, so + off + p.n_rad);
+      } else {
+        panel(gr, gwr, ph.ln_eps2, ph.ln_lam2, yo + off, Wo + off, so + off);
+      }
     }
   }
   std::vector<double> zeros((size_t)v.KS * v.Rbp * v.Qp, 0.0);
@@ -315,10 +392,14 @@ dse_status upload_tables(const dse_params& p, const Views& v, const Phys& ph, hi
       {v.TextT, TextT.data(), TextT.size() * 8},
       {v.xrow, xrow.data(), xrow.size() * 8},
       {v.ang, ang.data(), ang.size() * 8},
+      {v.yr, yr.data(), nr * 8},
+      {v.Wr, Wr.data(), nr * 8},
+      {v.syr, syr.data(), nr * 8},
       // the padding rows of B must be finite (they only feed padding rows of Eq)
       {v.Bm, zeros.data(), zeros.size() * 8},
   };
   for (auto& u_ : up) {
+    if (u_.bytes == 0) continue;
     const hipError_t e = hipMemcpyAsync(u_.dst, u_.src, u_.bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) { set_err(err, "table upload: %s", hipGetErrorString(e)); return DSE_E_DEVICE; }
   }
@@ -656,6 +737,10 @@ dse_status dse_vjp(dse_ctx* ctx, const double* d_c, const double* d_u, double* d
   if (!ctx) return DSE_E_INVALID;
   if (!d_c || !d_u || (!d_uJ && !d_utheta)) {
     set_err(ctx->err, "d_c, d_u and one of d_uJ, d_utheta are required");
+    return DSE_E_INVALID;
+  }
+  if (ctx->v.split) {
+    set_err(ctx->err, "dse_vjp: not available on split radial grids (DSE_QUAD_SPLIT)");
     return DSE_E_INVALID;
   }
   DeviceGuard dg(ctx->device);

@@ -51,6 +51,7 @@ struct Views {
   int nqt;               // radial tiles of 64 nodes per row (Qp / 64)
   int KS;                // angular slices: point-kernel blocks per (row, radial tile)
   int Rb, Rbp;           // rows of the B matrix (2 RZ + RG) and padded to 16
+  int split;             // 1: every row has its own radial grid, split at its x (Sec. 3)
   // tables
   double* coef;          // [2][NJ] a then b, zero padded, j = 0 term halved
   double* y;             // [Qp] radial nodes (padding: y = 1, W = 0)
@@ -65,10 +66,17 @@ struct Views {
   double* xrow;          // [RZ + RG] external momentum of each row
   double* lnX;           // [n] ln Z (gluon rows) / ln G (ghost rows) at x_r
   double* ang;           // [5][Kp] cos, sin^2(theta/2), v sin^2, v sin^4, sin^2
+  // split radial grids (split = 1; [RZ + RG][Qp], row order as xrow, padding W = 0)
+  double* yr;            // nodes
+  double* Wr;            // weights including the factor y
+  double* syr;           // mapped coordinate s(y), clamped to [-1, 1]
+  double* lnZyr;         // ln Z, ln G at the nodes (per assembly)
+  double* lnGyr;
   // per assembly
   // (in mixed precision Bm, Dp, Eq and Dgh hold FP32 values at the same indices)
   double* Bm;            // [KS][Rbp][Qp] angular sums per slice: rows gluon-a | gluon-b | ghost-b
-  double* Dp;            // [3][RZ or RG][nqt*KS][NJ] k-side partials: gluon-a | gluon-b | ghost-a
+  double* Dp;            // [3 or 4][RZ or RG][nqt*KS][NJ] k-side partials: gluon-a | gluon-b | ghost-a
+                         // (| ghost-b: the q-side of the ghost rows on split grids)
   double* Pip;           // [RZ + RG][nqt*KS][2] partial self-energies (sum, rounding error)
   double* Absp;          // [RZ + RG][nqt*KS] partial sums of |integrand|
   double* Eq;            // [kCS][Rbp][NJ] B . T (+ k-side sums for the gluon rows), by part

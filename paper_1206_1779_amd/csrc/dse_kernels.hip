@@ -172,6 +172,34 @@ __global__ __launch_bounds__(256) void dressing_kernel(Views v, Phys ph, const d
   dressing_body(v, ph, c, blockIdx.x * 256, gridDim.x * 256, blockIdx.x == 0);
 }
 
+// ln Z and ln G at the nodes of every row's own radial grid (the split at x,
+// Sec. 3): one thread per (row, node), the Chebyshev recurrence at the node's
+// mapped coordinate (a table) plus the IR power laws below eps2 (the grids end
+// at lambda2, so no UV extension).
+__global__ __launch_bounds__(256) void dressing_split_kernel(Views v, Phys ph, const double* __restrict__ c) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= (v.RZ + v.RG) * v.Qp) return;
+  const double s = v.syr[i];
+  const double s2 = s + s;
+  double z = 0.5 * c[0], g = 0.5 * c[v.n_z];
+  double Tp = 1.0, Tc = s;
+  const int nmax = v.n_z > v.n_g ? v.n_z : v.n_g;
+  for (int j = 1; j < nmax; ++j) {
+    if (j < v.n_z) z = fma(c[j], Tc, z);
+    if (j < v.n_g) g = fma(c[v.n_z + j], Tc, g);
+    const double Tn = fma(s2, Tc, -Tp);
+    Tp = Tc;
+    Tc = Tn;
+  }
+  const double ly = log(v.yr[i]);
+  if (ly < ph.ln_eps2) {
+    z += 2.0 * ph.kappa * (ly - ph.ln_eps2);
+    g += -ph.kappa * (ly - ph.ln_eps2);
+  }
+  v.lnZyr[i] = z;
+  v.lnGyr[i] = g;
+}
+
 // --------------------------------------------------------------------------
 // Reduce-scatter of NV values per lane over the lanes that share a slice
 // (lane bits log2(G) .. 5).  While the count is even a stage halves it: the
@@ -241,16 +269,23 @@ __host__ __device__ constexpr int point_smem() { return 528 + (BATCH ? 10 : 8) *
 // kind and so has few registers to spare: the coefficients are staged in LDS
 // and ln z comes from the library's log (the series below needs more
 // registers and cost the batch kernel half its occupancy).
-template <int KIND, int NJ, int MODE, bool MIX = false, bool BATCH = false>
+// SPLIT: every row has its own radial grid (the split at x of Sec. 3); the
+// q-side derivative, d integrand / d ln(dressing at y) times Tilde-T_j(s(y)),
+// then depends on the row as well and is accumulated here with the k-side
+// sums (each lane adds its angular sums B at its node y as one more point of
+// the k-side pass), so no B . T contraction follows.  FP64 only.
+template <int KIND, int NJ, int MODE, bool MIX = false, bool BATCH = false, bool SPLIT = false>
 __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int row, int tile,
                                            double* __restrict__ smem) {
   using TL = Tile<KIND, NJ>;
   using acc_t = typename std::conditional<MIX, float, double>::type;
   constexpr int G = TL::G;
   constexpr int JT = TL::JT;
-  constexpr int NT = KIND == GLUON ? 2 : 1;  // k-side targets
   constexpr bool JAC = MODE == MODE_JAC || MODE == MODE_VJP;  // B and D wanted
+  constexpr int NTA = KIND == GLUON ? 2 : 1;                   // k-side targets of the angle loop
+  constexpr int NT = KIND == GLUON || (SPLIT && JAC) ? 2 : 1;  // targets of D (ghost: b from the q-side)
   constexpr bool WEIGHTED = MODE == MODE_VJP || MODE == MODE_VTH;
+  static_assert(!SPLIT || (!MIX && !BATCH && !WEIGHTED), "the split radial grid is FP64 residual/Jacobian only");
 
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -262,10 +297,11 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
   const int growrow = KIND == GLUON ? row : v.RZ + row;  // index into xrow / Pip
 
   const double x = v.xrow[growrow];
-  const double y = v.y[q];
-  const double W = v.W[q];
-  const double lGy = v.lnGy[q];
-  const double lZy = v.lnZy[q];
+  const size_t qi = SPLIT ? (size_t)growrow * v.Qp + q : (size_t)q;
+  const double y = SPLIT ? v.yr[qi] : v.y[q];
+  const double W = SPLIT ? v.Wr[qi] : v.W[q];
+  const double lGy = SPLIT ? v.lnGyr[qi] : v.lnGy[q];
+  const double lZy = SPLIT ? v.lnZyr[qi] : v.lnZy[q];
 
   // per (row, node) constants: z = mx [(1-t)^2 + 4 t sin^2(theta/2)]
   const double mx = fmax(x, y), mn = fmin(x, y);
@@ -454,11 +490,64 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj) {
           Da[jj] = fma(pa, tc, Da[jj]);
-          if (NT == 2) Db[jj] = fma(pb, tc, Db[jj]);
+          if (NTA == 2) Db[jj] = fma(pb, tc, Db[jj]);
           const acc_t tn = fma(sr2, tc, -tp);
           tp = tc;
           tc = tn;
         }
+      }
+    }
+  }
+
+  if constexpr (SPLIT && JAC) {
+    // ---- q-side on the row's own grid: this wave's angular sums Ba, Bb at
+    // the lane's node y enter like one more point of the k-side pass, with the
+    // Chebyshev recurrence at s(y) (gluon rows: both targets; ghost rows: the
+    // b target only, d / d ln G(y))
+    const double sy = v.syr[qi];
+    const double sy2 = sy + sy;
+    double qtp[G], qtc[G];
+    {
+      double Tp = sy, Tc = 1.0;  // (T_{-1}, T_0)
+#pragma unroll
+      for (int m = 0; m < G; ++m) {
+        qtp[m] = Tp;
+        qtc[m] = Tc;
+#pragma clang loop unroll(disable)
+        for (int j = 0; j < JT; ++j) {
+          const double Tn = fma(sy2, Tc, -Tp);
+          Tp = Tc;
+          Tc = Tn;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      double tp, tc, pa, pb;
+      if (r == 0) {
+        tp = qtp[0]; tc = qtc[0];
+#pragma unroll
+        for (int m = 1; m < G; ++m) if (member == m) { tp = qtp[m]; tc = qtc[m]; }
+        pa = Ba; pb = Bb;
+      } else {
+        const int want = member ^ r;
+        double sp = qtp[0], sc = qtc[0];
+#pragma unroll
+        for (int m = 1; m < G; ++m) if (want == m) { sp = qtp[m]; sc = qtc[m]; }
+        tp = __shfl_xor(sp, r, 64);
+        tc = __shfl_xor(sc, r, 64);
+        pa = KIND == GLUON ? __shfl_xor((double)Ba, r, 64) : 0.0;
+        pb = __shfl_xor((double)Bb, r, 64);
+      }
+      const double sr = r == 0 ? sy : __shfl_xor(sy, r, 64);
+      const double sr2 = sr + sr;
+#pragma unroll
+      for (int jj = 0; jj < JT; ++jj) {
+        if (KIND == GLUON) Da[jj] = fma(pa, tc, Da[jj]);
+        Db[jj] = fma(pb, tc, Db[jj]);
+        const double tn = fma(sr2, tc, -tp);
+        tp = tc;
+        tc = tn;
       }
     }
   }
@@ -484,8 +573,10 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
 
   // ---- q-side: angular sums staged in LDS, reduced over the four waves
   acc_t (*bs)[4][64] = reinterpret_cast<acc_t (*)[4][64]>(smem + 16);
-  bs[0][wave][lane] = Ba;
-  bs[1][wave][lane] = Bb;
+  if (!SPLIT) {
+    bs[0][wave][lane] = Ba;
+    bs[1][wave][lane] = Bb;
+  }
   // ---- k-side: reduce-scatter over the lanes that hold the same slice, then
   // over the waves through LDS
   acc_t (*ds)[NT * NJ] = reinterpret_cast<acc_t (*)[NT * NJ]>(smem + 528);
@@ -510,7 +601,7 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     }
   }
   __syncthreads();
-  if (t < 64) {
+  if (!SPLIT && t < 64) {
     const acc_t sa_ = ((bs[0][0][t] + bs[0][1][t]) + bs[0][2][t]) + bs[0][3][t];
     const acc_t sb_ = ((bs[1][0][t] + bs[1][1][t]) + bs[1][2][t]) + bs[1][3][t];
     acc_t* Bk = reinterpret_cast<acc_t*>(v.Bm) + (size_t)ks * v.Rbp * v.Qp;
@@ -525,8 +616,9 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
     const int tg = o / NJ, j = o - tg * NJ;
     acc_t sum = ((ds[0][o] + ds[1][o]) + ds[2][o]) + ds[3][o];
     if (j == 0) sum *= (acc_t)0.5;  // Tilde-T_0 = 1/2
-    const int grp = KIND == GLUON ? tg : 2;
-    const size_t base = (size_t)grp * v.RZ * ntile * NJ;
+    // groups: gluon-a, gluon-b (RZ rows each), ghost-a, ghost-b (RG rows each)
+    const int grp_row0 = KIND == GLUON ? tg * v.RZ : 2 * v.RZ + tg * v.RG;
+    const size_t base = (size_t)grp_row0 * ntile * NJ;
     reinterpret_cast<acc_t*>(v.Dp)[base + ((size_t)row * ntile + tile) * NJ + j] = sum;
   }
 }
@@ -537,13 +629,13 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
 template <int KIND, int NJ, int MODE, bool MIX>
 constexpr int point_waves() { return KIND == GLUON && MODE == MODE_JAC && !MIX && NJ <= 64 ? 3 : 1; }
 
-template <int KIND, int NJ, int MODE, bool MIX>
+template <int KIND, int NJ, int MODE, bool MIX, bool SPLIT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(point_waves<KIND, NJ, MODE, MIX>())))
 void point_kernel(Views v, Phys ph) {
   __shared__ double smem[point_smem<NJ, false>()];
   const int ntile = v.nqt * v.KS;
   const int row = blockIdx.x / ntile;
-  point_body<KIND, NJ, MODE, MIX>(v, ph, row, blockIdx.x - row * ntile, smem);
+  point_body<KIND, NJ, MODE, MIX, false, SPLIT>(v, ph, row, blockIdx.x - row * ntile, smem);
 }
 
 // --------------------------------------------------------------------------
@@ -556,7 +648,10 @@ void point_kernel(Views v, Phys ph) {
 // part's radial range and meet in LDS) and add, for gluon rows, the k-side
 // partial sums of the same target; the remaining blocks reduce the ghost
 // rows' k-side partials into Dgh[p].
-template <bool MIX>
+// SPLIT (each row on its own radial grid): the q-side sums are already in the
+// k-side partials, so there is no product: Eq = the partial sums of the
+// gluon rows' targets and of the ghost rows' b target.
+template <bool MIX, bool SPLIT = false>
 __device__ __forceinline__ void contract_body(const Views& v, int bx, int by, int part) {
   using acc_t = typename std::conditional<MIX, float, double>::type;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -584,6 +679,21 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by, in
     return;
   }
   const int r0 = bx * 16, j0 = by * 16;
+  if constexpr (SPLIT) {
+    for (int e = t; e < 16 * 16; e += 256) {
+      const int row = r0 + (e >> 4), col = j0 + (e & 15);
+      double sum = 0.0;
+      if (row < 2 * v.RZ + v.RG) {
+        // groups gluon-a, gluon-b, ghost-a, ghost-b: ghost-b rows follow ghost-a
+        const int grow = row < 2 * v.RZ ? row : row + v.RG;
+        const double* src = reinterpret_cast<const double*>(Dp) + (size_t)grow * dstride + col;
+#pragma unroll 4
+        for (int k = tlo; k < thi; ++k) sum += src[(size_t)k * NJ];
+      }
+      reinterpret_cast<double*>(v.Eq)[((size_t)part * v.Rbp + row) * NJ + col] = sum;
+    }
+    return;
+  }
   const int qper = Qp / kCS / 4;
   const int qbeg = part * (Qp / kCS) + wave * qper;
   const int i = lane & 15, kk = lane >> 4;
@@ -638,9 +748,9 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by, in
   }
 }
 
-template <bool MIX>
+template <bool MIX, bool SPLIT = false>
 __global__ __launch_bounds__(256) void contract_kernel(Views v) {
-  contract_body<MIX>(v, blockIdx.x, blockIdx.y, blockIdx.z);
+  contract_body<MIX, SPLIT>(v, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 
@@ -1734,33 +1844,45 @@ __global__ __launch_bounds__(256) void batch_pack_kernel(const SolveDesc* __rest
 
 hipError_t launch_dressing(const Views& v, const Phys& ph, const double* c, hipStream_t st) {
   hipLaunchKernelGGL(dressing_kernel, dim3((v.Qp + v.n + 255) / 256), dim3(256), 0, st, v, ph, c);
+  if (v.split) {
+    const int cnt = (v.RZ + v.RG) * v.Qp;
+    hipLaunchKernelGGL(dressing_split_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, v, ph, c);
+  }
   return hipGetLastError();
 }
 
-template <int NJ, int MODE, bool MIX>
+template <int NJ, int MODE, bool MIX, bool SPLIT = false>
 static hipError_t points_nj(const Views& v, const Phys& ph, hipStream_t st, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL((point_kernel<GLUON, NJ, MODE, MIX>), dim3(v.RZ * v.nqt * v.KS), dim3(256), 0, st, v, ph);
+  hipLaunchKernelGGL((point_kernel<GLUON, NJ, MODE, MIX, SPLIT>), dim3(v.RZ * v.nqt * v.KS), dim3(256), 0, st, v,
+                     ph);
   if (ev) (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((point_kernel<GHOST, NJ, MODE, MIX>), dim3(v.RG * v.nqt * v.KS), dim3(256), 0, st, v, ph);
+  hipLaunchKernelGGL((point_kernel<GHOST, NJ, MODE, MIX, SPLIT>), dim3(v.RG * v.nqt * v.KS), dim3(256), 0, st, v,
+                     ph);
   if (ev) (void)hipEventRecord(ev[2], st);
   return hipGetLastError();
 }
 
-template <int MODE, bool MIX>
+template <int MODE, bool MIX, bool SPLIT = false>
 static hipError_t points_dispatch(const Views& v, const Phys& ph, hipStream_t st, hipEvent_t* ev) {
   switch (v.NJ) {
-    case 16: return points_nj<16, MODE, MIX>(v, ph, st, ev);
-    case 32: return points_nj<32, MODE, MIX>(v, ph, st, ev);
-    case 48: return points_nj<48, MODE, MIX>(v, ph, st, ev);
-    case 64: return points_nj<64, MODE, MIX>(v, ph, st, ev);
-    case 96: return points_nj<96, MODE, MIX>(v, ph, st, ev);
-    case 128: return points_nj<128, MODE, MIX>(v, ph, st, ev);
+    case 16: return points_nj<16, MODE, MIX, SPLIT>(v, ph, st, ev);
+    case 32: return points_nj<32, MODE, MIX, SPLIT>(v, ph, st, ev);
+    case 48: return points_nj<48, MODE, MIX, SPLIT>(v, ph, st, ev);
+    case 64: return points_nj<64, MODE, MIX, SPLIT>(v, ph, st, ev);
+    case 96: return points_nj<96, MODE, MIX, SPLIT>(v, ph, st, ev);
+    case 128: return points_nj<128, MODE, MIX, SPLIT>(v, ph, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_points(const Views& v, const Phys& ph, int mode, bool mix, hipStream_t st, hipEvent_t* ev) {
+  if (v.split) {
+    // the host admits only FP64 residual and Jacobian modes on a split grid
+    if (mode == MODE_RES) return points_dispatch<MODE_RES, false, true>(v, ph, st, ev);
+    if (mode == MODE_JAC && !mix) return points_dispatch<MODE_JAC, false, true>(v, ph, st, ev);
+    return hipErrorInvalidValue;
+  }
   switch (mode) {
     case MODE_RES: return points_dispatch<MODE_RES, false>(v, ph, st, ev);
     case MODE_JAC:
@@ -1774,10 +1896,14 @@ hipError_t launch_points(const Views& v, const Phys& ph, int mode, bool mix, hip
 hipError_t launch_contract(const Views& v, bool mix, hipStream_t st) {
   const int gh_blocks = (v.RG + 15) / 16;
   const dim3 grid(v.Rbp / 16 + gh_blocks, v.NJ / 16, kCS);
-  if (mix)
+  if (v.split) {
+    if (mix) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((contract_kernel<false, true>), grid, dim3(256), 0, st, v);
+  } else if (mix) {
     hipLaunchKernelGGL(contract_kernel<true>, grid, dim3(256), 0, st, v);
-  else
+  } else {
     hipLaunchKernelGGL(contract_kernel<false>, grid, dim3(256), 0, st, v);
+  }
   return hipGetLastError();
 }
 

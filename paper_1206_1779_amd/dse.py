@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libdse.so")
 
 ABI_VERSION = 1
 MAX_N = 128
+QUAD_TANH_SINH = 1  # dse_params.quad bits (include/dse.h)
+QUAD_SPLIT = 2
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "HIP device error", 3: "workspace too small",
           4: "singular Newton matrix", 5: "no convergence", 6: "non-finite"}
@@ -39,7 +41,7 @@ class Params(C.Structure):
     _fields_ = [
         ("abi_version", C.c_int32), ("n_z", C.c_int32), ("n_g", C.c_int32),
         ("n_rad", C.c_int32), ("n_ir", C.c_int32), ("n_ang", C.c_int32),
-        ("precision", C.c_int32), ("reserved_", C.c_int32),
+        ("precision", C.c_int32), ("quad", C.c_int32),
         ("eps2", C.c_double), ("lambda2", C.c_double), ("ir_efolds", C.c_double),
         ("alpha_mu", C.c_double), ("n_c", C.c_double), ("g0_inv", C.c_double),
         ("z_lambda_inv", C.c_double), ("kappa", C.c_double), ("delta", C.c_double),
