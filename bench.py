@@ -321,11 +321,53 @@ def bench_schwinger(dse, workloads, torch, with_cpu: bool = True) -> dict:
         tc0 = time.perf_counter()
         oracle.schwinger(p, c.cpu().numpy(), tt, n=nc, p_max=W["p_max"])
         t_all = time.perf_counter() - tc0
+        # the rule is O(n^2) (n recurrence steps per node), the sum O(n m)
         out["cpu_oracle"] = {"nodes": nc, "times": len(tt), "threads": oracle.get_threads(),
                              "gl_s": t_gl, "total_s": t_all,
-                             "total_s_extrapolated_to_nodes": t_all + t_gl * ((n / nc) ** 2 - 1)
-                             + (t_all - t_gl) * (n / nc - 1)}
+                             "total_s_extrapolated_to_nodes": t_gl * (n / nc) ** 2
+                             + max(t_all - t_gl, 0.0) * (n / nc)}
     return out
+
+
+def bench_discretisation(dse, workloads, torch) -> dict:
+    """Accuracy against cost of the two discretisations (the shared log-GL
+    radial grid with GL in theta, and the paper's split at x with tanh-sinh
+    angles, Sec. 2-3) on the scaling solution at the paper's parameters,
+    N = 24: per grid the device time of one Newton-matrix assembly, the Newton
+    solve, the largest error of ln Z and ln G at 64 log-spaced momenta in
+    [eps2, lambda2] and of N_c alpha(0) (IR fixed point 8.91512) against a
+    split + tanh-sinh reference with 256 nodes per radial interval and 257
+    angles."""
+    base = workloads.config("paper")
+    u = torch.logspace(-6, math.log10(5e4), 64, dtype=torch.float64, device="cuda:0")
+    u0 = torch.tensor([base["eps2"] * 1e-6], dtype=torch.float64, device="cuda:0")
+
+    def run(n_rad, n_ir, n_ang, quad):
+        s = dse.Solver(**dict(base, n_rad=n_rad, n_ir=n_ir, n_ang=n_ang, quad=quad))
+        s.newton()                 # loads the kernels
+        r = s.newton(extra_iters=2)  # timed: from the start guess, two steps past convergence
+        c = r.c
+        s.jacobian(c)
+        s.set_timing(True)
+        for _ in range(10):
+            s.jacobian(c)
+        st, _ = s.read_timings()
+        s.set_timing(False)
+        _, lz, lg = s.running_coupling(c, u)
+        a0, _, _ = s.running_coupling(c, u0)
+        return {"n_rad": n_rad, "n_ir": n_ir, "n_ang": n_ang, "quad": quad, "assembly_ms": sum(st),
+                "newton_ms": r.t_total_ms, "iters": r.iters, "status": r.status}, lz, lg, float(a0.item())
+
+    ref, lz0, lg0, _ = run(256, 256, 257, 3)
+    rows = []
+    for args in ((96, 24, 24, 0), (192, 48, 32, 0), (384, 96, 64, 0), (768, 192, 128, 0), (1536, 384, 256, 0),
+                 (32, 32, 33, 3), (64, 64, 65, 3), (128, 128, 129, 3)):
+        row, lz, lg, a0 = run(*args)
+        row["max_err_lnZ"] = float((lz - lz0).abs().max())
+        row["max_err_lnG"] = float((lg - lg0).abs().max())
+        row["alpha0_nc_rel_err"] = abs(base["n_c"] * a0 / 8.91512 - 1.0)
+        rows.append(row)
+    return {"workload": workloads.WORKLOAD_NAMES["paper"], "reference": ref, "grids": rows}
 
 
 def bench_mixed(dse, workloads, torch) -> dict:
@@ -455,7 +497,7 @@ def main() -> int:
     roof = {"bound": "alu", "kernel": "point_kernel<gluon, 64, jacobian>",
             "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-            "traffic": measured_traffic("void dse::point_kernel<0, 64, 1, false>"),
+            "traffic": measured_traffic("void dse::point_kernel<0, 64, 1, false, false>"),
             "flops_per_launch": a_gl, "avg_launch_ms": t_gl * 1e3, "launches": cnt,
             "timed": "HIP events around each launch over the second pass of the same steps",
             "ghost_kernel_ms": stages[2], "ghost_kernel_tflops": ghost_point_flops(cfg) / (stages[2] * 1e-3) / 1e12}
@@ -496,6 +538,7 @@ def main() -> int:
         out["coupling"] = bench_coupling(dse, workloads, torch)
         out["root_parity"] = bench_root_parity(dse, workloads, torch)
         out["schwinger"] = bench_schwinger(dse, workloads, torch, with_cpu=not args.no_cpu)
+        out["discretisation"] = bench_discretisation(dse, workloads, torch)
     if not args.no_cpu:
         cb = cpu_baseline(cfg, c.cpu().numpy())
         cb["gpu_speedup"] = value / cb["value"]

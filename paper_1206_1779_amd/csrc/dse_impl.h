@@ -151,7 +151,7 @@ hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, dou
 void lu_setup();  // LDS attributes of the factorisation kernels (call before any capture)
 
 // Observables (dse_observables.hip).  launch_gl: n-node Gauss-Legendre rule
-// into x, w; tab holds 16 (n - 1) bytes of recurrence coefficients.
+// into x, w; tab holds 8 (n - 1) bytes of recurrence coefficients.
 hipError_t launch_gl(int n, double* x, double* w, void* tab, hipStream_t st);
 int schwinger_chunks(int n);  // partial sums per time of the Schwinger sum
 hipError_t launch_schwinger(const Views& v, const Phys& ph, const double* c, int n, double p_max, const double* x,

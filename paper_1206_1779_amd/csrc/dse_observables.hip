@@ -16,104 +16,84 @@
 #include "dse_impl.h"
 
 namespace dse {
+
+constexpr int kGLGroup = 16;  // Gauss-Legendre recurrence steps whose coefficients are loaded together
+
 namespace {
 
 // ---------------------------------------------------------------------------
 // Gauss-Legendre rule.
 //
-// P_{k+1}(s) = alpha_k s P_k(s) - beta_k P_{k-1}(s), alpha_k = (2k+1)/(k+1),
-// beta_k = k/(k+1).  The coefficients come from a table (one pair per step,
-// read by all lanes at once), so a step is two multiplications off the
-// dependency chain and one FMA on it; there is no division in the loop.
+// P_{k+1}(s) = alpha_k s P_k(s) - beta_k P_{k-1}(s) with beta_k = k/(k+1) and
+// alpha_k = 1 + beta_k.  The beta_k come from a table, read by all lanes of a
+// wave at once through the scalar cache (no per-lane copies); a step is
+// v = beta s + s and q = beta P_{k-1} off the dependency chain (P_{k-1} is one
+// step old) and one FMA P_{k+1} = v P_k - q on it; no division in the loop.
 //
 // One lane per positive root (roots come in pairs +-x): root k counted from
 // +1, started at Tricomi's estimate (1 - (n-1)/(8 n^3)) cos(pi (4k-1)/(4n+2)).
 // Newton steps x <- x - P_n/P_n' until the step is below 1e-16, then one more
 // recurrence at the final node for P_n' and the weight
-// w = 2 / ((1 - x^2) P_n'^2), P_n' = n (x P_n - P_{n-1}) / (x^2 - 1).
-// A block's 256 lanes run their recurrences in step: the coefficients are
-// staged through LDS in chunks of kGLChunk steps (the next chunk's global
-// load is in flight while the current one is used), and the block keeps
-// iterating while any of its lanes has not finished.
+// w = 2 / ((1 - x^2) P_n'^2), P_n' = n (x P_n - P_{n-1}) / (x^2 - 1).  A
+// wave keeps iterating while any of its lanes has not finished.
 
-constexpr int kGLChunk = 1024;  // recurrence steps per LDS stage (4 per thread)
-constexpr int kGLHalf = 8;      // steps per register set of the software pipeline
 
-__global__ __launch_bounds__(256) void gl_table_kernel(int n, double2* __restrict__ tab) {
+// beta[k-1] = k/(k+1) for k = 1 .. n-1, then 2 kGLGroup zeros (the read-ahead
+// of the last group stays inside the table).
+__global__ __launch_bounds__(256) void gl_table_kernel(int n, double* __restrict__ beta) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;
-  if (k < n) {
-    const double kp = k + 1.0;
-    tab[k - 1] = make_double2((2.0 * k + 1.0) / kp, k / kp);
-  }
+  if (k < n) beta[k - 1] = k / (k + 1.0);
+  else if (k < n + 2 * kGLGroup) beta[k - 1] = 0.0;
 }
 
-__device__ __forceinline__ void gl_step(double2 ab, double s, double& p0, double& p1) {
-  const double v = ab.x * s;   // alpha_k s: independent of the chain
-  const double q = ab.y * p0;  // beta_k P_{k-1}: P_{k-1} is one step old
+__device__ __forceinline__ void gl_step(double b, double s, double& p0, double& p1) {
+  const double v = fma(b, s, s);  // alpha_k s
+  const double q = b * p0;        // beta_k P_{k-1}
   const double p2 = fma(v, p1, -q);
   p0 = p1;
   p1 = p2;
 }
 
-// (P_n(s), P_{n-1}(s)); every thread of the block calls it with the same n.
-// buf: two stages of kGLChunk coefficient pairs plus 2 kGLHalf of slack, so
-// the read-ahead of a stage's last group stays inside the array.
-__device__ __forceinline__ void legendre_block(int n, double s, const double2* __restrict__ tab,
-                                               double2 (*buf)[kGLChunk + 2 * kGLHalf], double& pn,
-                                               double& pn1) {
-  const int t = threadIdx.x;
+// (P_n(s), P_{n-1}(s)); every lane of the wave calls it with the same n.
+// Scalar loads complete out of order, so a wait covers every load in flight:
+// each group's first step (whose wait covers only that group's loads) runs
+// before the next group's loads are issued, and the rest of the group hides
+// their latency.
+__device__ __forceinline__ void legendre_wave(int n, double s, const double* __restrict__ beta, double& pn,
+                                              double& pn1) {
   const int steps = n - 1;
   double p0 = 1.0, p1 = s;
-  double2 nxt[kGLChunk / 256];
+  int k = 0;
+  if (steps >= 2 * kGLGroup) {
+    double A[kGLGroup], B[kGLGroup];
 #pragma unroll
-  for (int r = 0; r < kGLChunk / 256; ++r)
-    nxt[r] = t + 256 * r < steps ? tab[t + 256 * r] : make_double2(0.0, 0.0);
-  int ib = 0;
-  for (int c0 = 0; c0 < steps; c0 += kGLChunk, ib ^= 1) {
+    for (int u = 0; u < kGLGroup; ++u) A[u] = beta[u];
+    for (; k + 2 * kGLGroup <= steps; k += 2 * kGLGroup) {
+      gl_step(A[0], s, p0, p1);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int r = 0; r < kGLChunk / 256; ++r) buf[ib][t + 256 * r] = nxt[r];
-    __syncthreads();
-    // the next stage's global loads stay in flight while this one is used
+      for (int u = 0; u < kGLGroup; ++u) B[u] = beta[k + kGLGroup + u];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int r = 0; r < kGLChunk / 256; ++r) {
-      const int i = c0 + kGLChunk + t + 256 * r;
-      if (i < steps) nxt[r] = tab[i];
-    }
-    const double2* __restrict__ b = buf[ib];
-    const int cnt = steps - c0 < kGLChunk ? steps - c0 : kGLChunk;
-    if (cnt == kGLChunk) {
-      // two register sets: the LDS reads of one group are issued while the
-      // other group's steps run
-      double2 A[kGLHalf], B[kGLHalf];
+      for (int u = 1; u < kGLGroup; ++u) gl_step(A[u], s, p0, p1);
+      __builtin_amdgcn_sched_barrier(0);
+      gl_step(B[0], s, p0, p1);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < kGLHalf; ++u) A[u] = b[u];
-#pragma unroll 1
-      for (int u0 = 0; u0 < kGLChunk; u0 += 2 * kGLHalf) {
+      for (int u = 0; u < kGLGroup; ++u) A[u] = beta[k + 2 * kGLGroup + u];  // zero padded past the end
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < kGLHalf; ++u) B[u] = b[u0 + kGLHalf + u];
-        // keep each group's reads ahead of the other group's steps
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < kGLHalf; ++u) gl_step(A[u], s, p0, p1);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < kGLHalf; ++u) A[u] = b[u0 + 2 * kGLHalf + u];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < kGLHalf; ++u) gl_step(B[u], s, p0, p1);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    } else {
-      for (int u = 0; u < cnt; ++u) gl_step(b[u], s, p0, p1);
+      for (int u = 1; u < kGLGroup; ++u) gl_step(B[u], s, p0, p1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
+  for (; k < steps; ++k) gl_step(beta[k], s, p0, p1);
   pn = p1;
   pn1 = p0;
 }
 
-__global__ __launch_bounds__(256) void gl_node_kernel(int n, const double2* __restrict__ tab, double* __restrict__ x,
+__global__ __launch_bounds__(256) void gl_node_kernel(int n, const double* __restrict__ beta, double* __restrict__ x,
                                                       double* __restrict__ w) {
-  __shared__ double2 buf[2][kGLChunk + 2 * kGLHalf];
   const int nh = (n + 1) / 2;
   const int k = blockIdx.x * 256 + threadIdx.x + 1;
   const bool act = k <= nh;
@@ -122,9 +102,9 @@ __global__ __launch_bounds__(256) void gl_node_kernel(int n, const double2* __re
   if (act) s = (1.0 - (dn - 1.0) / (8.0 * dn * dn * dn)) * cos(kPi * (4.0 * k - 1.0) / (4.0 * dn + 2.0));
   bool done = !act, last = false;
   double dp = 1.0;
-  for (int it = 0; it < 100 && __syncthreads_or(done ? 0 : 1); ++it) {
+  for (int it = 0; it < 100 && __any(done ? 0 : 1); ++it) {
     double pn, pn1;
-    legendre_block(n, s, tab, buf, pn, pn1);
+    legendre_wave(n, s, beta, pn, pn1);
     const double d = dn * (s * pn - pn1) / (s * s - 1.0);
     if (!done) {
       if (last) {
@@ -315,10 +295,9 @@ __global__ __launch_bounds__(256) void renorm_kernel(Views v, Phys ph, const dou
 }  // namespace
 
 hipError_t launch_gl(int n, double* x, double* w, void* tab, hipStream_t st) {
-  if (n > 1)
-    hipLaunchKernelGGL(gl_table_kernel, dim3((n - 1 + 255) / 256), dim3(256), 0, st, n, (double2*)tab);
+  hipLaunchKernelGGL(gl_table_kernel, dim3((n - 1 + 2 * kGLGroup + 255) / 256), dim3(256), 0, st, n, (double*)tab);
   const int nh = (n + 1) / 2;
-  hipLaunchKernelGGL(gl_node_kernel, dim3((nh + 255) / 256), dim3(256), 0, st, n, (const double2*)tab, x, w);
+  hipLaunchKernelGGL(gl_node_kernel, dim3((nh + 255) / 256), dim3(256), 0, st, n, (const double*)tab, x, w);
   return hipGetLastError();
 }
 
@@ -353,7 +332,7 @@ constexpr int kGLMax = 1 << 24;
 constexpr int kRenormScan = 4096;
 
 size_t al256(size_t b) { return (b + 255) / 256 * 256; }
-size_t gl_tab_bytes(int n) { return al256((size_t)(n > 1 ? n - 1 : 1) * 2 * sizeof(double)); }
+size_t gl_tab_bytes(int n) { return al256((size_t)(n - 1 + 2 * dse::kGLGroup) * sizeof(double)); }
 
 struct SchwLayout {
   size_t tab, x, w, p, g, part, total;
