@@ -27,6 +27,7 @@
  */
 #include "dse_ref.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -712,10 +713,18 @@ int dse_ref_dF_dtheta(const dse_ref_params* p, const double* c, double* out) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Dense LU with partial pivoting (Doolittle, row interchanges).            */
+/* Dense LU with partial pivoting (Doolittle, row interchanges).  The matrix */
+/* counts as singular (status 4) when a pivot is zero, not finite, or at    */
+/* most n eps times the largest |entry| of its row of the input: singular   */
+/* to working precision, whatever the scale of each row.                    */
 int dse_ref_lu_solve(int n, double* A, double* b, double* x, int trans) {
   int* piv = (int*)malloc(sizeof(int) * n);
+  double* rm = (double*)malloc(sizeof(double) * n);
   int st = 0;
+  for (int i = 0; i < n; ++i) {
+    rm[i] = 0.0;
+    for (int j = 0; j < n; ++j) rm[i] = fmax(rm[i], fabs(A[(size_t)i * n + j]));
+  }
   for (int k = 0; k < n; ++k) {
     int pr = k;
     double best = fabs(A[(size_t)k * n + k]);
@@ -725,19 +734,23 @@ int dse_ref_lu_solve(int n, double* A, double* b, double* x, int trans) {
     }
     piv[k] = pr;
     if (!(best > 0.0) || !isfinite(best)) { st = 4; break; }
-    if (pr != k)
+    if (pr != k) {
       for (int j = 0; j < n; ++j) {
         double t = A[(size_t)k * n + j];
         A[(size_t)k * n + j] = A[(size_t)pr * n + j];
         A[(size_t)pr * n + j] = t;
       }
+      double t = rm[k]; rm[k] = rm[pr]; rm[pr] = t;
+    }
     double d = A[(size_t)k * n + k];
+    if (!(fabs(d) > n * DBL_EPSILON * rm[k])) { st = 4; break; }
     for (int i = k + 1; i < n; ++i) {
       double l = A[(size_t)i * n + k] / d;
       A[(size_t)i * n + k] = l;
       for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
     }
   }
+  free(rm);
   if (st) { free(piv); return st; }
   double* w = (double*)malloc(sizeof(double) * n);
   memcpy(w, b, sizeof(double) * n);

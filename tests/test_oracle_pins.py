@@ -419,6 +419,30 @@ def test_lu_singular(ref):
         ref.lu_solve(np.ones((3, 3)), np.ones(3))
 
 
+@pytest.mark.parametrize("case", workloads.near_singular_matrices(), ids=lambda c: c[0])
+def test_lu_relative_singularity(ref, case):
+    """The singular verdict is relative to each row: a one-ulp perturbation
+    of a singular matrix is singular at any row scaling; a well-conditioned
+    system whose rows (and right-hand side) span 1e-150..1e150 solves to the
+    accuracy numpy gets after equilibration; an 8-ulp pivot passes and its
+    solution is the exact one of the rounded matrix (closed form of the 2 x 2
+    inverse)."""
+    name, A, b, singular = case
+    if singular:
+        with pytest.raises(ref.OracleError):
+            ref.lu_solve(A, b)
+        return
+    x = ref.lu_solve(A, b)
+    if name == "eight_ulp":
+        d = 8 * 2.0 ** -52                                   # det, exact
+        xe = np.array([((1 + d) * b[0] - b[1]) / d, (b[1] - b[0]) / d])
+        assert np.max(np.abs(x - xe) / np.abs(xe)) < 1e-15
+    else:
+        s = np.max(np.abs(A), axis=1)
+        xe = np.linalg.solve(A / s[:, None], b / s)
+        assert np.max(np.abs(x - xe)) <= 1e-13 * np.max(np.abs(xe))
+
+
 # --------------------------------------------------------------------------- #
 # grid
 
@@ -614,18 +638,31 @@ def test_residual_scale_ghost_rows_equal_self_energy_magnitudes(ref):
         assert abs(S[p.n_z + i] - want) <= 1e-13 * want
 
 
-@pytest.mark.parametrize("name,max_iter", [("cfg1", 20), ("cfg2", 2)])
-def test_newton_from_unit_dressings_stalls(ref, name, max_iter):
-    """From c = 0 (G = Z = 1 on [eps2, Lambda^2]) the Newton direction is no
-    descent direction of the scaled residual: the relaxation collapses below
-    1e-6 and the merit stays above 0.5, which is why the solves start from
-    the asymptotic forms instead (the start from the asymptotic forms
-    converges, see the solution-level pins)."""
-    p = ref.params(**workloads.config(name))
-    c, rep = ref.newton(p, c0=np.zeros(p.n_z + p.n_g), max_iter=max_iter)
+def test_newton_from_unit_dressings_stalls(ref):
+    """From c = 0 (G = Z = 1 on [eps2, Lambda^2]) at N = 16 the Newton
+    direction is no descent direction of the scaled residual: the relaxation
+    collapses below 1e-6 and the merit stays above 0.5, which is why the
+    solves start from the asymptotic forms instead (the start from the
+    asymptotic forms converges, see the solution-level pins)."""
+    p = ref.params(**workloads.config("cfg1"))
+    c, rep = ref.newton(p, c0=np.zeros(p.n_z + p.n_g), max_iter=20)
     assert rep["status"] == 5
     assert min(rep["fnorm_hist"]) > 0.5
     assert max(rep["relax_hist"]) < 1e-6
+
+
+def test_newton_matrix_at_unit_dressings_is_singular_at_n64(ref):
+    """At N = 64 the Newton matrix at c = 0 is singular to working precision:
+    the smallest singular value of the row-equilibrated matrix (from the SVD,
+    not the LU) is below n eps of the largest, and the solve reports status
+    4 at its first LU instead of iterating."""
+    p = ref.params(**workloads.config("cfg2"))
+    c0 = np.zeros(p.n_z + p.n_g)
+    J = ref.jacobian(p, c0)
+    sv = np.linalg.svd(J / np.max(np.abs(J), axis=1)[:, None], compute_uv=False)
+    assert sv[-1] < len(c0) * 2.0 ** -52 * sv[0]
+    c, rep = ref.newton(p, c0=c0, max_iter=2)
+    assert rep["status"] == 4 and rep["iters"] == 0
 
 
 def test_stored_oracle_roots_solve_the_equations(ref):

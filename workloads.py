@@ -105,3 +105,22 @@ def perturbation(n_z: int, n_g: int, scale: float, seed: int) -> np.ndarray:
     da = rng.standard_normal(n_z) / (1.0 + np.arange(n_z))
     db = rng.standard_normal(n_g) / (1.0 + np.arange(n_g))
     return scale * np.concatenate([da, db])
+
+
+def near_singular_matrices() -> list:
+    """Dense systems on both sides of the LU's singularity test (a pivot at or
+    below n eps times the largest |entry| of its row): (name, A, b, singular).
+    The right-hand sides are 1, 2, ..., n scaled like the rows of A."""
+    u = 2.0 ** -52
+    rng = np.random.default_rng(5)
+    G = rng.standard_normal((6, 6)) + 4 * np.eye(6)
+    R = rng.integers(-4, 5, size=(5, 5)).astype(float)
+    R[2] = R[0] + R[1]  # rank deficient in real arithmetic
+    cases = [("one_ulp", np.array([[1.0, 1.0], [1.0, 1.0 + u]]), True),
+             ("one_ulp_row_scaled", np.array([[1e12, 1e12], [1.0, 1.0 + u]]), True),
+             ("eight_ulp", np.array([[1.0, 1.0], [1.0, 1.0 + 8 * u]]), False),
+             ("row_scaled_well_conditioned", np.diag([1e-150, 1e-75, 1.0, 1e75, 1e150, 1.0]) @ G, False),
+             ("rank_deficient_integers", R, True)]
+    return [(name, A, np.arange(1.0, A.shape[0] + 1) * np.max(np.abs(A), axis=1), sing)
+            for name, A, sing in cases]
+
