@@ -503,7 +503,7 @@ def main() -> int:
             "ghost_kernel_ms": stages[2], "ghost_kernel_tflops": ghost_point_flops(cfg) / (stages[2] * 1e-3) / 1e12}
 
     # s / Newton solve from the start guess to scaled residual < 1e-10
-    times, iters = [float("nan")], [0]
+    times, iters, split = [float("nan")], [0], (float("nan"), float("nan"))
     if args.solves > 0:
         times, iters = [], []
     for _ in range(args.solves):
@@ -513,6 +513,7 @@ def main() -> int:
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t1)
         iters.append(r.iters)
+        split = (r.t_assembly_ms, r.t_lu_ms)
 
     out = {
         "metric": "Jacobian entries/s + s/Newton-solve at N=64; batched & adjoint vs plain",
@@ -528,6 +529,7 @@ def main() -> int:
         "assembly_ms": t_asm * 1e3,
         "stage_ms": dict(zip(["dressing", "gluon_points", "ghost_points", "contract", "assemble"], stages)),
         "newton_solve_s": statistics.median(times), "newton_iters": iters[0],
+        "newton_solve_split_ms": {"assembly": split[0], "lu": split[1]},
         "roofline": roof,
     }
     if not args.no_extras:

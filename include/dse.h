@@ -54,7 +54,8 @@ typedef enum {
   DSE_E_INVALID = 1,   /* bad argument or parameter; nothing was launched      */
   DSE_E_DEVICE = 2,    /* HIP runtime error                                    */
   DSE_E_NOMEM = 3,     /* workspace smaller than dse_workspace_bytes()        */
-  DSE_E_SINGULAR = 4,  /* zero (or non-finite) pivot in the Newton LU          */
+  DSE_E_SINGULAR = 4,  /* a pivot of the Newton LU is zero, not finite, or at
+                          most n eps times the largest entry of its row         */
   DSE_E_NOCONV = 5,    /* Newton did not converge within max_iter             */
   DSE_E_NONFINITE = 6  /* residual or Jacobian not finite                      */
 } dse_status;
@@ -137,6 +138,9 @@ typedef struct {
   double t_total_ms;       /* wall time of the call                               */
   int32_t n_jacobians_mixed; /* of n_jacobians, those with FP32 derivative sums   */
   int32_t reserved2_;
+  double t_assembly_ms;    /* device time of the Newton-matrix assemblies (the
+                              first one: wall time including its norms)          */
+  double t_lu_ms;          /* device time of the LU solves                        */
 } dse_newton_report;
 
 /* Fills *p with the physics defaults above and the small grid
@@ -257,8 +261,9 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
  * workspace), the LU solve J Delta = F, d_c_new = d_c - rho Delta, and the
  * residual at d_c_new into d_F_new (and its scale into d_S_new, nullable).
  * Enqueued on the context's stream; returns without synchronising unless
- * check != 0, which synchronises and reports a zero pivot (DSE_E_SINGULAR;
- * d_c_new is then undefined).  d_c and d_c_new must differ.  With graphs on
+ * check != 0, which synchronises and reports a singular J (DSE_E_SINGULAR: a
+ * pivot zero, not finite, or at most n eps times the largest |J_rk| of its
+ * row; d_c_new is then undefined).  d_c and d_c_new must differ.  With graphs on
  * (dse_set_graphs, the default) the launch sequence is recorded into a HIP
  * graph on the first call for a given set of pointers and rho and replayed
  * afterwards; the arrays must stay allocated while the context uses them.
@@ -270,7 +275,10 @@ dse_status dse_set_graphs(dse_ctx* ctx, int32_t on);
 
 /* Solves J x = b (trans = 0) or J^T x = b (trans != 0) for a row-major
  * n x n d_J with the device LU (partial pivoting).  d_J is not modified; the
- * factors go to the workspace.  d_x may equal d_b. */
+ * factors go to the workspace.  d_x may equal d_b.  DSE_E_SINGULAR (d_x then
+ * undefined) when a pivot is zero, not finite, or at most n eps times the
+ * largest |entry| of its row of d_J: the test is relative to each row, so
+ * scaling a row of the system changes neither the solution nor the verdict. */
 dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, double* d_x,
                         int32_t trans);
 
@@ -280,13 +288,14 @@ dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, doub
  * (trans != 0) for a row-major n x n d_J, 1 <= n <= 2 * DSE_MAX_N, with the
  * same device LU (partial pivoting; results identical to dse_lu_solve).  d_J,
  * d_b (length n) are not modified; d_x (length n) may equal d_b.  d_info
- * (device int32, nullable) receives 0 or DSE_E_SINGULAR (zero or non-finite
- * pivot; d_x is then undefined).  Enqueued on hip_stream (a hipStream_t; NULL
- * = default stream) of the current device without synchronising; allocates
- * nothing.  Scratch: one static device array of 528 KiB per GPU (the padded
- * factors when they do not fit in LDS, the pivot rows, the status word when
- * d_info is NULL), taken by the first call on that GPU and kept until the
- * process ends.  Every call on a GPU shares that array: calls that overlap on
+ * (device int32, nullable) receives 0 or DSE_E_SINGULAR (a pivot zero, not
+ * finite, or at most n eps times the largest |entry| of its row of d_J; d_x is
+ * then undefined).  Enqueued on hip_stream (a hipStream_t; NULL = default
+ * stream) of the current device without synchronising; allocates nothing.
+ * Scratch: one static device array of 517.25 KiB per GPU (the padded factors
+ * when they do not fit in LDS, the pivot rows, the status word when d_info is
+ * NULL, the largest entry of each row), taken by the first call on that GPU
+ * and kept until the process ends.  Every call on a GPU shares that array: calls that overlap on
  * one GPU (several streams or threads at once) race.  Invalid n or NULL
  * d_J / d_b / d_x: DSE_E_INVALID before any launch, message in
  * dse_last_error(NULL). */

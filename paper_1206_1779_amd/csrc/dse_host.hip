@@ -248,6 +248,8 @@ size_t layout(const dse_params& p, Views* v, char* base, int ks) {
   t.LU = (double*)take(np16 * (np16 + 1) * d);  // padded [A | b] when it does not fit LDS
   t.piv = (int32_t*)take(t.n * sizeof(int32_t));
   t.flag = (int32_t*)take(4 * sizeof(int32_t));
+  t.rowmax = (double*)take(t.n * d);
+  t.rowmax_u = (double*)take(t.n * d);
   t.F = (double*)take(t.n * d);
   t.S = (double*)take(t.n * d);
   t.Ft = (double*)take(t.n * d);
@@ -614,6 +616,8 @@ dse_status dse_destroy(dse_ctx* ctx) {
     for (auto& e : row) (void)hipEventDestroy(e);
   for (auto& g : ctx->steps)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  for (auto& e : ctx->nev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
   delete ctx;
   return DSE_OK;
@@ -725,11 +729,15 @@ dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, doub
   if (!ctx) return DSE_E_INVALID;
   if (!d_J || !d_b || !d_x) { set_err(ctx->err, "NULL argument"); return DSE_E_INVALID; }
   DeviceGuard dg(ctx->device);
-  HIP_TRY(ctx, dse::launch_lu_solve(ctx->v, d_J, d_b, d_x, trans, ctx->st));
+  HIP_TRY(ctx, dse::launch_row_absmax(ctx->v.n, d_J, ctx->v.rowmax_u, ctx->st));
+  HIP_TRY(ctx, dse::launch_lu_solve(ctx->v, d_J, d_b, d_x, trans, ctx->st, nullptr, 0.0, nullptr, ctx->v.rowmax_u));
   int32_t flag = 0;
   HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
-  if (flag == DSE_E_SINGULAR) { set_err(ctx->err, "zero pivot"); return DSE_E_SINGULAR; }
+  if (flag == DSE_E_SINGULAR) {
+    set_err(ctx->err, "singular matrix: a pivot is zero, not finite, or below n eps times its row's largest entry");
+    return DSE_E_SINGULAR;
+  }
   return DSE_OK;
 }
 
@@ -789,7 +797,7 @@ dse_status enqueue_step(dse_ctx* ctx, const double* c, double rho, double* c_new
   dse_status s = DSE_OK;
   if (!reuse) s = eval_jacobian(ctx, c, v.J, v.F, v.S);
   if (s == DSE_OK) {
-    const hipError_t e = dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, ctx->st, c, rho, c_new);
+    const hipError_t e = dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, ctx->st, c, rho, c_new, v.rowmax);
     if (e != hipSuccess) {
       set_err(ctx->err, "LU launch: %s", hipGetErrorString(e));
       s = DSE_E_DEVICE;
@@ -905,8 +913,10 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
   // J, F, S at the start: every evaluation of an accepted point is an
   // assembly, so the next step's matrix comes with the residual that accepts it
   double nrm[4];
+  const auto ta = std::chrono::steady_clock::now();
   dse_status s = eval_jacobian(ctx, d_c, v.J, v.F, v.S, use_mix ? 1 : 0);
   if (s == DSE_OK) s = read_norms(ctx, v.F, v.S, nullptr, nrm);
+  r.t_assembly_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
   ++r.n_jacobians;
   if (use_mix) ++r.n_jacobians_mixed;
   bool have_J = true;      // v.J belongs to d_c
@@ -926,21 +936,35 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
     if (it >= o.max_iter) { status = DSE_E_NOCONV; break; }
     if (!have_J || j_mix != use_mix) {
       // after a relaxed step, or when the precision of the matrix changes
+      if (!ctx->nev[0])
+        for (auto& e : ctx->nev) HIP_TRY(ctx, hipEventCreate(&e));
+      HIP_TRY(ctx, hipEventRecord(ctx->nev[0], st));
       if ((s = eval_jacobian(ctx, d_c, v.J, v.F, v.S, use_mix ? 1 : 0)) != DSE_OK) { status = s; break; }
+      HIP_TRY(ctx, hipEventRecord(ctx->nev[1], st));
+      HIP_TRY(ctx, hipEventSynchronize(ctx->nev[1]));
+      float ma = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ma, ctx->nev[0], ctx->nev[1]));
+      r.t_assembly_ms += ma;
       ++r.n_jacobians;
       if (use_mix) ++r.n_jacobians_mixed;
       j_mix = use_mix;
     }
     if (hipGetLastError() != hipSuccess) { status = DSE_E_DEVICE; break; }
     // the solve also writes the full step c - Delta (the update kernel's FMA)
-    HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, st, d_c, 1.0, v.ct));
+    if (!ctx->nev[0])
+      for (auto& e : ctx->nev) HIP_TRY(ctx, hipEventCreate(&e));
+    HIP_TRY(ctx, hipEventRecord(ctx->nev[2], st));
+    HIP_TRY(ctx, dse::launch_lu_solve(v, v.J, v.F, v.dlt, 0, st, d_c, 1.0, v.ct, v.rowmax));
+    HIP_TRY(ctx, hipEventRecord(ctx->nev[3], st));
     const bool conv = f < o.tol;
     double rho = 1.0, ft = INFINITY, ft2 = INFINITY, dinf = 0.0;
     int32_t flag = 0;
     for (int h = 0;; ++h) {
       if (h == 0) {
         // the full step in Jacobian mode: accepted, its matrix is the next one
+        HIP_TRY(ctx, hipEventRecord(ctx->nev[0], st));
         if ((s = eval_jacobian(ctx, v.ct, v.J, v.F, v.S, use_mix ? 1 : 0)) != DSE_OK) { status = s; break; }
+        HIP_TRY(ctx, hipEventRecord(ctx->nev[1], st));
         ++r.n_jacobians;
         if (use_mix) ++r.n_jacobians_mixed;
         have_J = true;
@@ -955,7 +979,19 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
         have_J = false;
       }
       if ((s = read_norms(ctx, v.F, v.S, v.dlt, nrm)) != DSE_OK) { status = s; break; }
-      if (h == 0 && flag == DSE_E_SINGULAR) { status = DSE_E_SINGULAR; set_err(ctx->err, "zero pivot"); break; }
+      if (h == 0) {
+        // read_norms synchronised the stream: the phase events are complete
+        float ma = 0.f, ml = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ma, ctx->nev[0], ctx->nev[1]));
+        HIP_TRY(ctx, hipEventElapsedTime(&ml, ctx->nev[2], ctx->nev[3]));
+        r.t_assembly_ms += ma;
+        r.t_lu_ms += ml;
+      }
+      if (h == 0 && flag == DSE_E_SINGULAR) {
+        status = DSE_E_SINGULAR;
+        set_err(ctx->err, "singular Newton matrix: a pivot is zero, not finite, or below n eps times its row's largest entry");
+        break;
+      }
       ft = isfinite(nrm[0]) ? nrm[0] : INFINITY;
       ft2 = isfinite(nrm[0]) && isfinite(nrm[3]) ? nrm[3] : INFINITY;
       dinf = nrm[2];

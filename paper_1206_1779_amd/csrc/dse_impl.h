@@ -86,6 +86,8 @@ struct Views {
   double* LU;            // [np][np+1], np = 16 ceil(n/16): padded factors of [A | b] when they do not fit LDS
   int32_t* piv;          // [n]
   int32_t* flag;         // [4] status flags written by kernels
+  double* rowmax;        // [n] largest |J_rk| of each row of the Newton matrix (written by the assembly)
+  double* rowmax_u;      // [n] the same for a caller's matrix (dse_lu_solve)
   double* F;             // [n]
   double* S;             // [n]
   double* Ft;            // [n]
@@ -145,9 +147,14 @@ hipError_t launch_axpy(int n, const double* c, double rho, const double* d, doub
 hipError_t launch_copy2(int n, const double* a, double* ao, const double* b /* nullable */, double* bo,
                         hipStream_t st);
 // With cout != nullptr the solve also writes the update cout = cin - rho x.
+// rowmax (nullable): the largest |A_rk| of each row; a pivot at or below
+// n eps rowmax of its row then counts as singular (else only zero or
+// non-finite pivots do).
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x,
                            int trans, hipStream_t st, const double* cin = nullptr, double rho = 0.0,
-                           double* cout = nullptr);
+                           double* cout = nullptr, const double* rowmax = nullptr);
+// rowmax[r] = max_k |A[r][k]| of a row-major n x n matrix (one wave per row).
+hipError_t launch_row_absmax(int n, const double* A, double* rowmax, hipStream_t st);
 void lu_setup();  // LDS attributes of the factorisation kernels (call before any capture)
 
 // Observables (dse_observables.hip).  launch_gl: n-node Gauss-Legendre rule
@@ -204,6 +211,8 @@ struct dse_ctx {
   static constexpr int kRing = 64;
   static constexpr int kEv = 6;
   hipEvent_t ev[kRing][kEv];
+  // device time of the assembly and LU phases of dse_newton_solve
+  hipEvent_t nev[4] = {nullptr, nullptr, nullptr, nullptr};
   int ring_count;
   double acc_ms[5];
   int acc_n;

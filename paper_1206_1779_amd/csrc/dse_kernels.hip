@@ -110,6 +110,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // --------------------------------------------------------------------------
 // dressing: coef (c_0 halved, zero padded), ln Z / ln G at radial nodes and at
 // the collocation points.
@@ -819,6 +825,7 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
   const double d = exp(-v.lnX[r]);
   const double* Tx = v.Text + (size_t)r * NJ;
   double* Jr = J + (size_t)r * n;
+  double amax = 0.0;
   if (gl) {
     const int sub = v.RZ - 1;
     const acc_t* Ea = Eq;
@@ -832,6 +839,7 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
         val = -sum_parts(Eb + (size_t)i * NJ + j, es) + sum_parts(Eb + (size_t)sub * NJ + j, es);
       }
       Jr[c] = val;
+      amax = fmax(amax, fabs(val));
     }
   } else {
     const int sub = v.RG - 1;
@@ -845,7 +853,16 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
         val = -d * Tx[j] - sum_parts(Eb + (size_t)i * NJ + j, es) + sum_parts(Eb + (size_t)sub * NJ + j, es);
       }
       Jr[c] = val;
+      amax = fmax(amax, fabs(val));
     }
+  }
+  if (v.rowmax) {
+    // the row's largest |entry|: the scale of the LU's relative pivot test
+    __shared__ double red[4];
+    amax = wave_max(amax);
+    if ((t & 63) == 0) red[t >> 6] = amax;
+    __syncthreads();
+    if (t == 0) v.rowmax[r] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   }
   if (F && t < 64) row_residual_wave(v, ph, r, F, S, t);
 }
@@ -1365,7 +1382,8 @@ template <bool IN_LDS, int MR>
 __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, const double* __restrict__ b,
                                         double* x, double* __restrict__ Aglob, int* piv, int trans, int* flag,
                                         double* lds, const double* __restrict__ cin = nullptr, double rho = 0.0,
-                                        double* __restrict__ cout = nullptr) {
+                                        double* __restrict__ cout = nullptr,
+                                        const double* __restrict__ rowmax = nullptr) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
@@ -1484,6 +1502,15 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       for (int m = 0; m < MR; ++m)
         if (lpos[m] >= 0) sh.rmap[lpos[m]] = phys[m];
     }
+    __syncthreads();
+  }
+  if (rowmax && !sh.sing) {
+    // relative test: a pivot at or below n eps times the largest entry of
+    // its row in the input counts as singular (rows never move, so the
+    // pivot at position k belongs to input row rmap[k])
+    const double tol = n * 2.220446049250313e-16;
+    for (int k = t; k < n; k += 256)
+      if (!(fabs(sh.dinv[k]) * tol * rowmax[sh.rmap[k]] < 1.0)) sh.sing = 1;
     __syncthreads();
   }
   if (sh.sing) {
@@ -1615,9 +1642,21 @@ constexpr int kLUStaticBytes = (int)sizeof(LUShared) + 256;
 template <bool IN_LDS, int MR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void lu_solve_kernel(
     int n, const double* __restrict__ Ain, const double* __restrict__ b, double* x, double* __restrict__ Aglob,
-    int* piv, int trans, int* flag, const double* __restrict__ cin, double rho, double* __restrict__ cout) {
+    int* piv, int trans, int* flag, const double* __restrict__ cin, double rho, double* __restrict__ cout,
+    const double* __restrict__ rowmax) {
   extern __shared__ double lds[];
-  lu_body<IN_LDS, MR>(n, Ain, b, x, Aglob, piv, trans, flag, lds, cin, rho, cout);
+  lu_body<IN_LDS, MR>(n, Ain, b, x, Aglob, piv, trans, flag, lds, cin, rho, cout, rowmax);
+}
+
+// rowmax[r] = max_k |A[r][k]|, one wave per row.
+__global__ __launch_bounds__(256) void row_absmax_kernel(int n, const double* __restrict__ A,
+                                                         double* __restrict__ rowmax) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= n) return;
+  double m = 0.0;
+  for (int k = lane; k < n; k += 64) m = fmax(m, fabs(A[(size_t)r * n + k]));
+  m = wave_max(m);
+  if (lane == 0) rowmax[r] = m;
 }
 
 // --------------------------------------------------------------------------
@@ -1800,7 +1839,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int b = blockIdx.x;
   if (!mask[b]) return;
   const Views& v = d[b].v;
-  lu_body<IN_LDS, MR>(v.n, v.J, v.F, v.dlt, v.LU, v.piv, 0, flags + b, lds);
+  lu_body<IN_LDS, MR>(v.n, v.J, v.F, v.dlt, v.LU, v.piv, 0, flags + b, lds, nullptr, 0.0, nullptr, v.rowmax);
 }
 
 __global__ __launch_bounds__(256) void batch_axpy_kernel(const SolveDesc* __restrict__ d,
@@ -1919,10 +1958,14 @@ hipError_t launch_vjp_reduce(const Views& v, const double* u, double* uJ, double
 
 hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S, bool mix,
                            hipStream_t st) {
+  // the row maxima belong to the workspace's Newton matrix: a Jacobian
+  // written elsewhere leaves them alone
+  Views w = v;
+  if (J != v.J) w.rowmax = nullptr;
   if (mix)
-    hipLaunchKernelGGL(assemble_kernel<true>, dim3(v.n), dim3(256), 0, st, v, ph, J, F, S);
+    hipLaunchKernelGGL(assemble_kernel<true>, dim3(v.n), dim3(256), 0, st, w, ph, J, F, S);
   else
-    hipLaunchKernelGGL(assemble_kernel<false>, dim3(v.n), dim3(256), 0, st, v, ph, J, F, S);
+    hipLaunchKernelGGL(assemble_kernel<false>, dim3(v.n), dim3(256), 0, st, w, ph, J, F, S);
   return hipGetLastError();
 }
 
@@ -1999,8 +2042,13 @@ void lu_setup() {
   g_max_lds = val;
 }
 
+hipError_t launch_row_absmax(int n, const double* A, double* rowmax, hipStream_t st) {
+  hipLaunchKernelGGL(row_absmax_kernel, dim3((n + 3) / 4), dim3(256), 0, st, n, A, rowmax);
+  return hipGetLastError();
+}
+
 hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, double* x, int trans,
-                           hipStream_t st, const double* cin, double rho, double* cout) {
+                           hipStream_t st, const double* cin, double rho, double* cout, const double* rowmax) {
   const int n = v.n;
   const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
   // factors of [A | b], padded, in dynamic LDS when they fit
@@ -2012,17 +2060,17 @@ hipError_t launch_lu_solve(const Views& v, const double* A, const double* b, dou
   if (np <= 128) {
     if (fits)
       hipLaunchKernelGGL((lu_solve_kernel<true, 2>), dim3(1), dim3(256), lds_bytes, st, n, A, b, x, v.LU, v.piv,
-                         trans, v.flag, cin, rho, cout);
+                         trans, v.flag, cin, rho, cout, rowmax);
     else
       hipLaunchKernelGGL((lu_solve_kernel<false, 2>), dim3(1), dim3(256), 0, st, n, A, b, x, v.LU, v.piv, trans,
-                         v.flag, cin, rho, cout);
+                         v.flag, cin, rho, cout, rowmax);
   } else {
     if (fits)
       hipLaunchKernelGGL((lu_solve_kernel<true, 4>), dim3(1), dim3(256), lds_bytes, st, n, A, b, x, v.LU, v.piv,
-                         trans, v.flag, cin, rho, cout);
+                         trans, v.flag, cin, rho, cout, rowmax);
     else
       hipLaunchKernelGGL((lu_solve_kernel<false, 4>), dim3(1), dim3(256), 0, st, n, A, b, x, v.LU, v.piv, trans,
-                         v.flag, cin, rho, cout);
+                         v.flag, cin, rho, cout, rowmax);
   }
   return hipGetLastError();
 }

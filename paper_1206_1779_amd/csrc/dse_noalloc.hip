@@ -1,7 +1,8 @@
 // dse_noalloc.hip -- the dense LU solve of the Newton step for callers that
 // cannot allocate device memory (code under stream capture, tight serving
 // loops, harnesses that forbid hipMalloc).  Its scratch -- the padded factors
-// of [A | b] when they do not fit in LDS, the pivot rows and the status word --
+// of [A | b] when they do not fit in LDS, the pivot rows, the status word and
+// the largest entry of each row (for the relative pivot test) --
 // lives in one static device array per GPU, held until the process ends.
 
 #include <hip/hip_runtime.h>
@@ -18,12 +19,13 @@ constexpr size_t kLuBytes =
     (size_t)((kMaxN + kLuNB - 1) / kLuNB * kLuNB) * ((kMaxN + kLuNB - 1) / kLuNB * kLuNB + 1) * sizeof(double);
 constexpr size_t kPivOff = (kLuBytes + 255) / 256 * 256;
 constexpr size_t kFlagOff = kPivOff + (kMaxN * sizeof(int32_t) + 255) / 256 * 256;
-constexpr size_t kScratchBytes = kFlagOff + 256;
+constexpr size_t kRowOff = kFlagOff + 256;
+constexpr size_t kScratchBytes = kRowOff + kMaxN * sizeof(double);
 constexpr int kMaxDevices = 64;
 
 }  // namespace
 
-// 528 KiB per GPU.  In host code this name is only a handle for
+// 517.25 KiB per GPU.  In host code this name is only a handle for
 // hipGetSymbolAddress: the device address comes from that call.
 static __device__ __align__(256) char scratch[kScratchBytes];
 
@@ -75,7 +77,10 @@ extern "C" dse_status dse_lu_solve_noalloc(int32_t n, const double* d_J, const d
   v.LU = (double*)base;
   v.piv = (int32_t*)(base + kPivOff);
   v.flag = d_info ? d_info : (int32_t*)(base + kFlagOff);
-  const hipError_t e = dse::launch_lu_solve(v, d_J, d_b, d_x, trans, (hipStream_t)hip_stream);
+  double* rowmax = (double*)(base + kRowOff);
+  hipError_t e = dse::launch_row_absmax(n, d_J, rowmax, (hipStream_t)hip_stream);
+  if (e == hipSuccess)
+    e = dse::launch_lu_solve(v, d_J, d_b, d_x, trans, (hipStream_t)hip_stream, nullptr, 0.0, nullptr, rowmax);
   if (e != hipSuccess) {
     dse::set_err(dse::global_err(), "LU launch: %s", hipGetErrorString(e));
     return DSE_E_DEVICE;

@@ -59,7 +59,8 @@ class NewtonReport(C.Structure):
                 ("fnorm2", C.c_double), ("fnorm_hist", C.c_double * 128),
                 ("relax_hist", C.c_double * 128), ("n_jacobians", C.c_int32),
                 ("n_residuals", C.c_int32), ("t_total_ms", C.c_double),
-                ("n_jacobians_mixed", C.c_int32), ("reserved2_", C.c_int32)]
+                ("n_jacobians_mixed", C.c_int32), ("reserved2_", C.c_int32),
+                ("t_assembly_ms", C.c_double), ("t_lu_ms", C.c_double)]
 
 
 class BatchTuning(C.Structure):
@@ -210,6 +211,8 @@ class NewtonResult:
     n_residuals: int = 0
     t_total_ms: float = 0.0
     n_jacobians_mixed: int = 0
+    t_assembly_ms: float = 0.0
+    t_lu_ms: float = 0.0
 
 
 class Solver:
@@ -379,7 +382,8 @@ class Solver:
                             fnorm2=rep.fnorm2, fnorm_hist=list(rep.fnorm_hist[: rep.iters + 1]),
                             relax_hist=list(rep.relax_hist[: rep.iters]),
                             n_jacobians=rep.n_jacobians, n_residuals=rep.n_residuals,
-                            t_total_ms=rep.t_total_ms, n_jacobians_mixed=rep.n_jacobians_mixed)
+                            t_total_ms=rep.t_total_ms, n_jacobians_mixed=rep.n_jacobians_mixed,
+                            t_assembly_ms=rep.t_assembly_ms, t_lu_ms=rep.t_lu_ms)
 
     def newton_step(self, c, rho: float = 1.0, out=None, check: bool = False):
         """One Newton iteration: returns (c_new, F(c_new), S(c_new)).  `out`

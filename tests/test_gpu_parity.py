@@ -149,10 +149,14 @@ def test_newton_parity(ref, dse, name):
     assert res.status == 0
     assert res.fnorm < 1e-13
     assert abs(res.iters - gold["iters"]) <= 1
+    # the report's device-time split: assemblies and LU solves inside the call
+    assert res.t_assembly_ms > 0 and res.t_lu_ms > 0
+    assert res.t_assembly_ms + res.t_lu_ms <= res.t_total_ms
     err, rel, elem = _root_errors(_np(res.c), gold)
     _note("  max coefficient difference %.3e (relative %.3e, largest elementwise %.3e), bound %.3e, "
-          "oracle floor %.3e, iters gpu %d oracle %d"
-          % (err, rel, elem, gold["bound"], gold["floor"], res.iters, gold["iters"]))
+          "oracle floor %.3e, iters gpu %d oracle %d; assembly %.3f ms, LU %.3f ms of %.3f ms"
+          % (err, rel, elem, gold["bound"], gold["floor"], res.iters, gold["iters"], res.t_assembly_ms,
+             res.t_lu_ms, res.t_total_ms))
     assert err <= 0.5 * gold["bound"]
 
 
@@ -212,6 +216,29 @@ def test_lu_singular(dse):
     with pytest.raises(dse.DSEError) as e:
         s.lu_solve(torch.ones(4, 4, dtype=torch.float64), torch.ones(4, dtype=torch.float64))
     assert e.value.status == 4
+
+
+@pytest.mark.parametrize("case", workloads.near_singular_matrices(), ids=lambda c: c[0])
+@pytest.mark.parametrize("trans", [False, True])
+def test_lu_relative_singularity(ref, dse, case, trans):
+    """The device LU takes the oracle's singular verdict (a pivot at or below
+    n eps times its row's largest entry) on matrices on both sides of it, at
+    row scalings from 1e-150 to 1e150, and otherwise its solution."""
+    import torch
+    name, A, b, singular = case
+    _note("lu relative %s trans=%d" % (name, trans))
+    n = A.shape[0]
+    s = dse.Solver(**workloads.config("cfg1", n_z=n // 2, n_g=n - n // 2))
+    if singular:
+        with pytest.raises(ref.OracleError):
+            ref.lu_solve(A, b, trans=trans)
+        with pytest.raises(dse.DSEError) as e:
+            s.lu_solve(A, b, trans=trans)
+        assert e.value.status == 4
+        return
+    xr = ref.lu_solve(A, b, trans=trans)
+    x = _np(s.lu_solve(A, b, trans=trans))
+    assert np.max(np.abs(x - xr)) <= 1e-13 * np.max(np.abs(xr)), np.max(np.abs(x - xr)) / np.max(np.abs(xr))
 
 
 def test_deterministic(dse):

@@ -83,3 +83,24 @@ def test_noalloc_singular_and_limits(dse):
     with pytest.raises(dse.DSEError) as e:
         dse.lu_solve_noalloc(torch.eye(257, dtype=torch.float64, device="cuda:0"), big, big.clone())
     assert e.value.status == 1 and "257" in str(e.value)
+
+
+@pytest.mark.parametrize("case", workloads.near_singular_matrices(), ids=lambda c: c[0])
+def test_noalloc_relative_singularity(ref, dse, case):
+    """Same verdict and solution as the oracle on matrices on both sides of
+    the relative pivot test."""
+    import torch
+    name, A, b, singular = case
+    info = torch.full((1,), -1, dtype=torch.int32, device="cuda:0")
+    Ad = torch.tensor(A, dtype=torch.float64, device="cuda:0")
+    bd = torch.tensor(b, dtype=torch.float64, device="cuda:0")
+    x = torch.empty_like(bd)
+    dse.lu_solve_noalloc(Ad, bd, x, info=info)
+    torch.cuda.synchronize()
+    if singular:
+        assert int(info.item()) == 4
+        return
+    assert int(info.item()) == 0
+    xr = ref.lu_solve(A, b)
+    assert np.max(np.abs(x.cpu().numpy() - xr)) <= 1e-13 * np.max(np.abs(xr))
+
