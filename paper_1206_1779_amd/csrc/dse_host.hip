@@ -471,7 +471,8 @@ dse_status eval_residual(dse_ctx* ctx, const double* c, double* F, double* S) {
 dse_status flush_timings(dse_ctx* ctx);
 
 // mix < 0: the context's precision; 0: FP64; 1: FP32 derivative sums
-dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, double* S, int mix_override = -1) {
+dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, double* S, int mix_override = -1,
+                         double* F2 = nullptr, double* S2 = nullptr) {
   const dse::Views& v = ctx->v;
   hipEvent_t* ev = nullptr;
   if (ctx->timing) {
@@ -487,7 +488,7 @@ dse_status eval_jacobian(dse_ctx* ctx, const double* c, double* J, double* F, do
   HIP_TRY(ctx, dse::launch_points(v, ctx->ph, 1, mix, ctx->st, ev ? ev + 1 : nullptr));
   HIP_TRY(ctx, dse::launch_contract(v, mix, ctx->st));
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[4], ctx->st));
-  HIP_TRY(ctx, dse::launch_assemble(v, ctx->ph, J, F, S, mix, ctx->st));
+  HIP_TRY(ctx, dse::launch_assemble(v, ctx->ph, J, F, S, mix, ctx->st, F2, S2));
   if (ev) HIP_TRY(ctx, hipEventRecord(ev[5], ctx->st));
   return DSE_OK;
 }
@@ -788,7 +789,7 @@ namespace {
 // The kernels of one Newton step: [J, F, S at c into the workspace, unless
 // they are held there already (reuse)]; LU solve J Delta = F with the update
 // c_new = c - rho Delta; J, F, S at c_new into the workspace (the matrix the
-// next step starts from); F, S copied to the caller's vectors.
+// next step starts from), F and S also into the caller's vectors.
 dse_status enqueue_step(dse_ctx* ctx, const double* c, double rho, double* c_new, double* F_new, double* S_new,
                         bool reuse, bool capturing) {
   const dse::Views& v = ctx->v;
@@ -803,11 +804,10 @@ dse_status enqueue_step(dse_ctx* ctx, const double* c, double rho, double* c_new
       s = DSE_E_DEVICE;
     }
   }
-  if (s == DSE_OK) s = eval_jacobian(ctx, c_new, v.J, v.F, v.S);
+  // the assembly at c_new also writes F and S to the caller's vectors
+  if (s == DSE_OK) s = eval_jacobian(ctx, c_new, v.J, v.F, v.S, -1, F_new, S_new);
   ctx->timing = timing;
-  if (s != DSE_OK) return s;
-  HIP_TRY(ctx, dse::launch_copy2(v.n, v.F, F_new, S_new ? v.S : nullptr, S_new, ctx->st));
-  return DSE_OK;
+  return s;
 }
 
 }  // namespace

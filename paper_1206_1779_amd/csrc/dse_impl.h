@@ -128,8 +128,9 @@ hipError_t launch_points(const Views& v, const Phys& ph, int mode, bool mix, hip
 hipError_t launch_contract(const Views& v, bool mix, hipStream_t st);
 hipError_t launch_row_weights(const Views& v, const double* u, hipStream_t st);
 hipError_t launch_vjp_reduce(const Views& v, const double* u, double* uJ, double* uth, hipStream_t st);
+// F2, S2 (nullable): second copies of F and S (a caller's vectors).
 hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S, bool mix,
-                           hipStream_t st);
+                           hipStream_t st, double* F2 = nullptr, double* S2 = nullptr);
 hipError_t launch_residual_rows(const Views& v, const Phys& ph, double* F, double* S,
                                 hipStream_t st);
 hipError_t launch_norms(const Views& v, const double* F, const double* S, const double* d,
@@ -144,8 +145,6 @@ hipError_t launch_fd_column(int n, const double* Fp, const double* Fm, const dou
                             hipStream_t st);
 hipError_t launch_axpy(int n, const double* c, double rho, const double* d, double* out,
                        hipStream_t st);
-hipError_t launch_copy2(int n, const double* a, double* ao, const double* b /* nullable */, double* bo,
-                        hipStream_t st);
 // With cout != nullptr the solve also writes the update cout = cin - rho x.
 // rowmax (nullable): the largest |A_rk| of each row; a pivot at or below
 // n eps rowmax of its row then counts as singular (else only zero or

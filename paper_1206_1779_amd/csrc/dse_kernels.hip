@@ -766,7 +766,8 @@ __global__ __launch_bounds__(256) void contract_kernel(Views v) {
 // its subtraction row (compensated sums of the (sum, error) pairs), then a
 // fixed-order wave reduction.
 __device__ __forceinline__ void row_residual_wave(const Views& v, const Phys& ph, int r, double* F,
-                                                  double* S, int lane) {
+                                                  double* S, int lane, double* F2 = nullptr,
+                                                  double* S2 = nullptr) {
   const bool gl = r < v.n_z;
   const int rr = gl ? r : v.RZ + (r - v.n_z);          // row in xrow / Pip
   const int sub = gl ? v.RZ - 1 : v.RZ + v.RG - 1;      // subtraction row
@@ -791,8 +792,12 @@ __device__ __forceinline__ void row_residual_wave(const Views& v, const Phys& ph
   if (lane == 0) {
     const double d = exp(-v.lnX[r]);
     const double par = gl ? ph.z_lambda_inv : ph.g0_inv;
-    F[r] = d - par - (xs + xc) + (ss + sc);
-    if (S) S[r] = fabs(d) + fabs(par) + ax + as;
+    const double f = d - par - (xs + xc) + (ss + sc);
+    const double sc_ = fabs(d) + fabs(par) + ax + as;
+    F[r] = f;
+    if (S) S[r] = sc_;
+    if (F2) F2[r] = f;   // second copies for a caller's vectors
+    if (S2) S2[r] = sc_;
   }
 }
 
@@ -813,7 +818,7 @@ __device__ __forceinline__ double sum_parts(const T* p, size_t stride) {
 
 template <bool MIX>
 __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, int r, double* __restrict__ J,
-                                              double* F, double* S) {
+                                              double* F, double* S, double* F2 = nullptr, double* S2 = nullptr) {
   using acc_t = typename std::conditional<MIX, float, double>::type;
   const acc_t* __restrict__ Eq = reinterpret_cast<const acc_t*>(v.Eq);
   const acc_t* __restrict__ Dgh = reinterpret_cast<const acc_t*>(v.Dgh);
@@ -864,13 +869,13 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
     __syncthreads();
     if (t == 0) v.rowmax[r] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   }
-  if (F && t < 64) row_residual_wave(v, ph, r, F, S, t);
+  if (F && t < 64) row_residual_wave(v, ph, r, F, S, t, F2, S2);
 }
 
 template <bool MIX>
 __global__ __launch_bounds__(256) void assemble_kernel(Views v, Phys ph, double* __restrict__ J,
-                                                       double* F, double* S) {
-  assemble_body<MIX>(v, ph, blockIdx.x, J, F, S);
+                                                       double* F, double* S, double* F2, double* S2) {
+  assemble_body<MIX>(v, ph, blockIdx.x, J, F, S, F2, S2);
 }
 
 // --------------------------------------------------------------------------
@@ -1023,16 +1028,6 @@ __global__ void axpy_kernel(int n, const double* c, double rho, const double* d,
   if (i < n) out[i] = fma(-rho, d[i], c[i]);
 }
 
-// ao = a and (when bo != nullptr) bo = b, n entries each.
-__global__ void copy2_kernel(int n, const double* __restrict__ a, double* __restrict__ ao,
-                             const double* __restrict__ b, double* __restrict__ bo) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    ao[i] = a[i];
-    if (bo) bo[i] = b[i];
-  }
-}
-
 // --------------------------------------------------------------------------
 // FP64 LU with partial pivoting and the triangular solves, one workgroup of
 // four waves; the padded matrix [A | b] lives in LDS (or in global memory
@@ -1127,51 +1122,121 @@ struct LUPivot {
   double inv;  // 1 / pivot
 };
 
+// Maximum of an unsigned key over the wave, returned uniformly (the same
+// rotations and row broadcasts as wave_max_nonneg, on 32-bit lanes).  Lanes
+// outside ROW_MASK read 0, the identity of the maximum, so the DPP move
+// folds into the maximum (one instruction per step).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned dpp_u(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+
+__device__ __forceinline__ unsigned umax_(unsigned a, unsigned b) { return a > b ? a : b; }
+
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = umax_(v, dpp_u<0x121, 0xf>(v));  // row_ror:1
+  v = umax_(v, dpp_u<0x122, 0xf>(v));  // row_ror:2
+  v = umax_(v, dpp_u<0x124, 0xf>(v));  // row_ror:4
+  v = umax_(v, dpp_u<0x128, 0xf>(v));  // row_ror:8
+  v = umax_(v, dpp_u<0x142, 0xa>(v));  // row_bcast:15 into rows 1 and 3
+  v = umax_(v, dpp_u<0x143, 0xc>(v));  // row_bcast:31 into rows 2 and 3
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// 1 / x for any x: the significand's reciprocal (x = m 2^e, |m| in [1/2, 1),
+// where the refined hardware estimate is within 1 ulp) scaled by 2^-e
+// exactly; zero, infinite or NaN x give a non-finite result.  No branch.
+__device__ __forceinline__ double recip_any(double x) {
+  const double m = __builtin_amdgcn_frexp_mant(x);
+  const int e = __builtin_amdgcn_frexp_exp(x);
+  return __builtin_amdgcn_ldexp(recip(m), -e);
+}
+
+// Pivot of column O: the largest |P[m][O]| over the rows not yet used; among
+// equal maxima the first register row (lowest m), then the lowest lane.  The
+// wave reduction runs on the leading 32 bits of each lane's largest |value|
+// (for non-negative doubles their order is the order of the values, up to
+// ties): when one lane holds the largest key it holds the maximum; when
+// several do, the exact maximum among them is reduced in FP64 and the first
+// register row holding it found by ballots (that lane's own first row holding
+// its maximum is the same row).  Every lane forms the reciprocal of its own
+// candidate while the reduction runs; the pivot lane's is read afterwards.
 template <int MR, int O>
 __device__ __forceinline__ LUPivot lu_pivot(const double (&P)[MR][LU_NB], const int (&lpos)[MR], int kc,
                                             int& sing) {
   double cand[MR];
   double lmax = -1.0;
+  int lm = 0;
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     cand[m] = lpos[m] >= kc ? fabs(P[m][O]) : -1.0;  // rows not yet used as pivots
-    lmax = fmax(lmax, cand[m]);
+    if (cand[m] > lmax) {
+      lmax = cand[m];
+      lm = m;
+    }
   }
-  const double gmax = wave_max_nonneg(lmax);
-  sing |= (!(gmax > 0.0) || isinf(gmax)) ? 1 : 0;
-  int lp = -1, mp = 0;
-#pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    const unsigned long long mk = __ballot(cand[m] == gmax);
-    if (lp < 0 && mk) { lp = (int)__builtin_ctzll(mk); mp = m; }
-  }
-  lp &= 63;  // no maximum only when singular: any lane
-  int lsel = lpos[0];
-  double psel = P[0][O];
+  double pl = P[0][O];
+  int ll = lpos[0];
 #pragma unroll
   for (int m = 1; m < MR; ++m)
-    if (mp == m) { lsel = lpos[m]; psel = P[m][O]; }
+    if (lm == m) {
+      pl = P[m][O];
+      ll = lpos[m];
+    }
+  const double il = recip_any(pl);
+  const unsigned key = lmax >= 0.0 ? (unsigned)((unsigned long long)__double_as_longlong(lmax) >> 32) : 0u;
+  const unsigned kmax = wave_max_u32(key);
+  // the reciprocal is materialised after the reduction and before the branch
+  // below (not sunk past it), so that its latency overlaps the reduction
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::"v"(il));
+  const unsigned long long tied = __ballot(key == kmax);
+  int lp = (int)__builtin_ctzll(tied);
+  if (__popcll(tied) != 1) {
+    const double gmax = wave_max_nonneg(key == kmax ? lmax : -1.0);
+    int f = -1;
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      const unsigned long long mk = __ballot(cand[m] == gmax);
+      if (f < 0 && mk) f = (int)__builtin_ctzll(mk);
+    }
+    lp = f & 63;  // no maximum only when singular: any lane
+  }
   LUPivot r;
   r.lp = lp;
-  r.mp = mp;
-  r.p = __builtin_amdgcn_readlane(lsel, lp);
-  r.inv = 1.0 / readlane_d(psel, lp);
+  r.mp = MR == 1 ? 0 : __builtin_amdgcn_readlane(lm, lp);
+  r.p = __builtin_amdgcn_readlane(ll, lp);
+  r.inv = readlane_d(il, lp);
+  // a zero, infinite or NaN pivot leaves a non-finite or zero reciprocal
+  sing |= (!(fabs(r.inv) < __builtin_huge_val()) || r.inv == 0.0) ? 1 : 0;
   return r;
 }
 
-// Entry cc of the pivot row, read across lanes from the lane that holds it
-// (cc is a constant once the callers' loops are unrolled).
-template <int MR>
-__device__ __forceinline__ double lu_prow(const double (&P)[MR][LU_NB], const LUPivot& pv, int cc) {
-  double sel = P[0][cc];
+// Entries FROM .. LU_NB - 1 of the pivot row, read across lanes from the lane
+// that holds it.  The register row mp is uniform, so the choice is one scalar
+// branch around lane reads of one row (readlane cannot be speculated, so the
+// branch stays), not a select per entry.
+template <int MR, int FROM>
+__device__ __forceinline__ void lu_prow(const double (&P)[MR][LU_NB], const LUPivot& pv, double (&rp)[LU_NB]) {
+  if constexpr (MR == 1) {
 #pragma unroll
-  for (int m = 1; m < MR; ++m) if (pv.mp == m) sel = P[m][cc];
-  return readlane_d(sel, pv.lp);
+    for (int cc = FROM; cc < LU_NB; ++cc) rp[cc] = readlane_d(P[0][cc], pv.lp);
+  } else {
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      if (pv.mp == m) {
+#pragma unroll
+        for (int cc = FROM; cc < LU_NB; ++cc) rp[cc] = readlane_d(P[m][cc], pv.lp);
+      }
+    }
+  }
 }
 
+// B(O): interchange, multipliers of column O, update of column O + 1; the
+// pivot row's entries O + 1 .. 15 are read here (rp) for C(O) as well.
 template <int MR, int O>
 __device__ __forceinline__ void lu_stage_b(double (&P)[MR][LU_NB], int (&lpos)[MR], const LUPivot& pv, int kc,
-                                           int lane, int& mypiv, double& myinv) {
+                                           int lane, int& mypiv, double& myinv, double (&rp)[LU_NB]) {
   mypiv = lane == O ? pv.p : mypiv;
   myinv = lane == O ? pv.inv : myinv;
 #pragma unroll
@@ -1179,56 +1244,59 @@ __device__ __forceinline__ void lu_stage_b(double (&P)[MR][LU_NB], int (&lpos)[M
     const int q = lpos[m];
     lpos[m] = q == kc ? pv.p : (q == pv.p ? kc : q);
   }
-  double r1 = 0.0;
-  if constexpr (O + 1 < LU_NB) r1 = lu_prow<MR>(P, pv, O + 1);
+  if constexpr (O + 1 < LU_NB) lu_prow<MR, O + 1>(P, pv, rp);
 #pragma unroll
   for (int m = 0; m < MR; ++m) {
     const bool below = lpos[m] > kc;
     const double l = below ? P[m][O] * pv.inv : 0.0;
     if (below) P[m][O] = l;
-    if constexpr (O + 1 < LU_NB) P[m][O + 1] = fma(-l, r1, P[m][O + 1]);
+    if constexpr (O + 1 < LU_NB) P[m][O + 1] = fma(-l, rp[O + 1], P[m][O + 1]);
   }
 }
 
+// C(O): the update of columns O + 2 .. 15 with the multipliers B(O) stored
+// and the pivot row's entries rp that B(O) read.
 template <int MR, int O>
-__device__ __forceinline__ void lu_stage_c(double (&P)[MR][LU_NB], const int (&lpos)[MR], const LUPivot& pv,
-                                           int kc) {
+__device__ __forceinline__ void lu_stage_c(double (&P)[MR][LU_NB], const int (&lpos)[MR],
+                                           const double (&rp)[LU_NB], int kc) {
   if constexpr (O + 2 < LU_NB) {
-    double rp[LU_NB];
-#pragma unroll
-    for (int cc = O + 2; cc < LU_NB; ++cc) rp[cc] = lu_prow<MR>(P, pv, cc);
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
-      const double l = lpos[m] > kc ? P[m][O] : 0.0;  // the multiplier B(O) stored
+      const double l = lpos[m] > kc ? P[m][O] : 0.0;
 #pragma unroll
       for (int cc = O + 2; cc < LU_NB; ++cc) P[m][cc] = fma(-l, rp[cc], P[m][cc]);
     }
   }
 }
 
+// rp: the pivot-row entries of column O - 1, read by B(O - 1).
 template <int MR, int O>
 __device__ __forceinline__ void lu_pipe(double (&P)[MR][LU_NB], int (&lpos)[MR], int k0, int lane, int& sing,
-                                        int& mypiv, double& myinv, const LUPivot& prev) {
+                                        int& mypiv, double& myinv, const double (&rp)[LU_NB]) {
   const LUPivot pv = lu_pivot<MR, O>(P, lpos, k0 + O, sing);
-  if constexpr (O > 0) lu_stage_c<MR, O - 1>(P, lpos, prev, k0 + O - 1);
-  lu_stage_b<MR, O>(P, lpos, pv, k0 + O, lane, mypiv, myinv);
-  if constexpr (O + 1 < LU_NB) lu_pipe<MR, O + 1>(P, lpos, k0, lane, sing, mypiv, myinv, pv);
+  if constexpr (O > 0) lu_stage_c<MR, O - 1>(P, lpos, rp, k0 + O - 1);
+  double rp_next[LU_NB];
+  lu_stage_b<MR, O>(P, lpos, pv, k0 + O, lane, mypiv, myinv, rp_next);
+  if constexpr (O + 1 < LU_NB) lu_pipe<MR, O + 1>(P, lpos, k0, lane, sing, mypiv, myinv, rp_next);
 }
 
 // Loads the rows of the panel at k0 (positions k0 ..) into wave 0's registers
 // and factors it; lpos/phys return each register row's new position and its
 // physical row (the caller publishes them to the row map).  FIRST: the panel
 // at 0, read straight from the n x n input (identity padding, identity row
-// map) instead of from M.
-template <int MR, bool FIRST>
+// map) instead of from M.  R <= MR register rows per lane hold the np - k0
+// rows left (R 64 >= np - k0); register rows R .. MR-1 return no row.
+template <int MR, bool FIRST, int R = MR>
 __device__ __forceinline__ void lu_factor_panel(double* M, int ld, int np, const int* rmap, int k0, int lane,
                                                 LUShared& sh, int (&lpos)[MR], int (&phys)[MR], int& sg,
                                                 const double* __restrict__ Ain = nullptr, int n = 0) {
-  double P[MR][LU_NB];
+  static_assert(R >= 1 && R <= MR, "register rows");
+  double P[R][LU_NB];
+  int lp_[R];
 #pragma unroll
-  for (int m = 0; m < MR; ++m) {
+  for (int m = 0; m < R; ++m) {
     const int pos = k0 + lane + 64 * m;
-    lpos[m] = pos < np ? pos : -1;  // -1: no row (never a candidate, never updated)
+    lp_[m] = pos < np ? pos : -1;  // -1: no row (never a candidate, never updated)
     if (FIRST) {
       phys[m] = pos < np ? pos : 0;
 #pragma unroll
@@ -1240,16 +1308,22 @@ __device__ __forceinline__ void lu_factor_panel(double* M, int ld, int np, const
       for (int c = 0; c < LU_NB; ++c) P[m][c] = pos < np ? M[(size_t)phys[m] * ld + k0 + c] : 0.0;
     }
   }
+#pragma unroll
+  for (int m = R; m < MR; ++m) {
+    lpos[m] = -1;
+    phys[m] = 0;
+  }
   sg = 0;
   int mypiv = 0;
   double myinv = 0.0;
-  const LUPivot none{0, 0, 0, 0.0};
-  lu_pipe<MR, 0>(P, lpos, k0, lane, sg, mypiv, myinv, none);
+  const double none[LU_NB] = {};  // no column before the first
+  lu_pipe<R, 0>(P, lp_, k0, lane, sg, mypiv, myinv, none);
   // the factored panel back to its physical rows; interchanges and
   // reciprocal pivots from lanes 0 .. 15
 #pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    if (lpos[m] >= 0) {
+  for (int m = 0; m < R; ++m) {
+    lpos[m] = lp_[m];
+    if (lp_[m] >= 0) {
       double* Mr = M + (size_t)phys[m] * ld + k0;
 #pragma unroll
       for (int cc = 0; cc < LU_NB; ++cc) Mr[cc] = P[m][cc];
@@ -1259,6 +1333,24 @@ __device__ __forceinline__ void lu_factor_panel(double* M, int ld, int np, const
     sh.spiv[k0 + lane] = mypiv;
     sh.dinv[k0 + lane] = myinv;
   }
+}
+
+// A later panel (at k0 > 0) with as many register rows per lane as its rows
+// need: fewer rows, fewer selects and updates per column.
+template <int MR>
+__device__ __forceinline__ void lu_factor_next(double* M, int ld, int np, const int* rmap, int k0, int lane,
+                                               LUShared& sh, int (&lpos)[MR], int (&phys)[MR], int& sg) {
+  const int rows = np - k0;
+  if constexpr (MR >= 4) {
+    if (rows > 192) { lu_factor_panel<MR, false, 4>(M, ld, np, rmap, k0, lane, sh, lpos, phys, sg); return; }
+  }
+  if constexpr (MR >= 3) {
+    if (rows > 128) { lu_factor_panel<MR, false, 3>(M, ld, np, rmap, k0, lane, sh, lpos, phys, sg); return; }
+  }
+  if constexpr (MR >= 2) {
+    if (rows > 64) { lu_factor_panel<MR, false, 2>(M, ld, np, rmap, k0, lane, sh, lpos, phys, sg); return; }
+  }
+  lu_factor_panel<MR, false, 1>(M, ld, np, rmap, k0, lane, sh, lpos, phys, sg);
 }
 
 // U12 = L11^{-1} A12 for the columns [jc, jc + ncols) (ncols <= 16): lanes
@@ -1475,7 +1567,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
     __syncthreads();
     if (wave == 0) {
       int sg;
-      lu_factor_panel<MR, false>(M, ld, np, rmap, j0, lane, sh, lpos, phys, sg);
+      lu_factor_next<MR>(M, ld, np, rmap, j0, lane, sh, lpos, phys, sg);
       if (sg && lane == 0) sh.sing = 1;
     } else {
       // a block's U12 rows, written by lanes 0-15, are read by every lane of
@@ -1957,15 +2049,15 @@ hipError_t launch_vjp_reduce(const Views& v, const double* u, double* uJ, double
 }
 
 hipError_t launch_assemble(const Views& v, const Phys& ph, double* J, double* F, double* S, bool mix,
-                           hipStream_t st) {
+                           hipStream_t st, double* F2, double* S2) {
   // the row maxima belong to the workspace's Newton matrix: a Jacobian
   // written elsewhere leaves them alone
   Views w = v;
   if (J != v.J) w.rowmax = nullptr;
   if (mix)
-    hipLaunchKernelGGL(assemble_kernel<true>, dim3(v.n), dim3(256), 0, st, w, ph, J, F, S);
+    hipLaunchKernelGGL(assemble_kernel<true>, dim3(v.n), dim3(256), 0, st, w, ph, J, F, S, F2, S2);
   else
-    hipLaunchKernelGGL(assemble_kernel<false>, dim3(v.n), dim3(256), 0, st, w, ph, J, F, S);
+    hipLaunchKernelGGL(assemble_kernel<false>, dim3(v.n), dim3(256), 0, st, w, ph, J, F, S, F2, S2);
   return hipGetLastError();
 }
 
@@ -2003,11 +2095,6 @@ hipError_t launch_fd_shift(int n, const double* c, int j, double h_rel, double s
 hipError_t launch_fd_column(int n, const double* Fp, const double* Fm, const double* hbuf, int j, double* J,
                             hipStream_t st) {
   hipLaunchKernelGGL(fd_column_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Fp, Fm, hbuf, j, J);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy2(int n, const double* a, double* ao, const double* b, double* bo, hipStream_t st) {
-  hipLaunchKernelGGL(copy2_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, a, ao, b, bo);
   return hipGetLastError();
 }
 
