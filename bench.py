@@ -169,7 +169,7 @@ def bench_batched(dse, workloads, torch) -> dict:
             "max_rel_coeff_diff_vs_plain": dmax, "jacobian_entries_per_round": entries,
             "assembly_round_ms": tune["best_ms"],
             "assembly_entries_per_s": entries / (tune["best_ms"] * 1e-3),
-            "launch": {k: tune[k] for k in ("slices", "persistent_blocks", "order")},
+            "launch": {k: tune[k] for k in ("slices", "persistent_blocks", "order", "tiles_per_item", "fused")},
             "launch_candidates": tune["candidates"]}
 
 

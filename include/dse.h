@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define DSE_ABI_VERSION 1
+#define DSE_ABI_VERSION 2
 /* largest Chebyshev order per function */
 #define DSE_MAX_N 128
 
@@ -367,6 +367,14 @@ typedef struct {
   int32_t cand_blocks[32];
   int32_t cand_order[32];
   double cand_ms[32];
+  int32_t tiles_per_item;     /* partial tiles (64 radial nodes x one angular slice)
+                                 of one row per queue item                            */
+  int32_t fused;              /* 1: dressings, points, contraction and assembly rows
+                                 in one cooperative launch of persistent_blocks
+                                 resident workgroups, stages separated by grid-wide
+                                 barriers; 0: one launch per stage                    */
+  int32_t cand_tiles[32];
+  int32_t cand_fused[32];
 } dse_batch_tuning;
 
 size_t dse_batch_workspace_bytes(const dse_params* p, int32_t count);
@@ -389,13 +397,26 @@ dse_status dse_batch_jacobian(dse_batch* b, const double* d_c, double* d_J, doub
  * says which). */
 dse_status dse_batch_newton_solve(dse_batch* b, double* d_c, const dse_newton_opts* opts,
                                   dse_newton_report* h_reports);
-/* Times every launch candidate (slices 1, 2, 4 as the angular grid allows;
- * one workgroup per item or persistent workgroups filling the device; queue
- * largest first or in problem order) on the family's Newton-matrix assembly at
- * d_c and keeps the fastest.  h_out nullable. */
+/* Times every launch candidate on the family's Newton-matrix assembly at d_c
+ * (Sec. 5 studies the GPU block size by hand; this searches the launch
+ * instead): angular slices 1, 2, 4 as the angular grid allows x one workgroup
+ * per queue item, persistent workgroups filling the device, or the fused
+ * cooperative launch (when the device offers cooperative launches) x 1, 2 or
+ * 4 partial tiles per queue item, queue largest first; then problem order for
+ * the best of them.  Keeps the fastest.  h_out nullable. */
 dse_status dse_batch_autotune(dse_batch* b, const double* d_c, dse_batch_tuning* h_out);
-/* Sets (or reads back) the launch explicitly; slices a power of two within
- * what the angular grid allows. */
+/* Sets (or reads back) the launch explicitly: slices a power of two within
+ * what the angular grid allows; tiles_per_item in [1, 64]; fused = 1 needs a
+ * device with cooperative launches and 1 <= persistent_blocks <= the number of
+ * workgroups that can be resident at once (else DSE_E_INVALID, message names
+ * the limit).  The fused form changes the Newton-matrix assembly only; the
+ * residual passes run staged with the same persistent workgroups.  Results
+ * are bit-identical across launch forms with the same slices. */
+dse_status dse_batch_set_launch_ex(dse_batch* b, int32_t slices, int32_t persistent_blocks, int32_t order,
+                                   int32_t tiles_per_item, int32_t fused);
+dse_status dse_batch_get_launch_ex(const dse_batch* b, int32_t* slices, int32_t* persistent_blocks,
+                                   int32_t* order, int32_t* tiles_per_item, int32_t* fused);
+/* The same with tiles_per_item = 1 and fused = 0. */
 dse_status dse_batch_set_launch(dse_batch* b, int32_t slices, int32_t persistent_blocks, int32_t order);
 dse_status dse_batch_get_launch(const dse_batch* b, int32_t* slices, int32_t* persistent_blocks,
                                 int32_t* order);

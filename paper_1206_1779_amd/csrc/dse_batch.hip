@@ -46,7 +46,10 @@ struct dse_batch {
   int slices = 1;
   int grid = 0;   // 0: one workgroup per item; > 0: persistent workgroups
   int order = 1;  // 1: largest first, 0: problem order
+  int tpi = 1;    // partial tiles per queue item
+  int fused = 0;  // 1: the whole assembly in one cooperative launch of grid workgroups
   int ncu = 256;
+  int coop = 0;   // the device supports cooperative launches
   dse::BatchArgs args{};
   std::vector<int> h_mask;
   std::vector<double> h_rho;
@@ -111,10 +114,12 @@ double item_cost(const dse::Views& v, int kind) {
   return kind == 0 ? pts * (2.0 * nmax + 4.0 * (v.n_z + v.n_g) + 100.0) : pts * (6.0 * v.n_z + 60.0);
 }
 
-dse_status set_launch(dse_batch* B, int slices, int grid, int order) {
+dse_status set_launch(dse_batch* B, int slices, int grid, int order, int tpi = 1, int fused = 0) {
   B->slices = slices;
   B->grid = grid;
   B->order = order;
+  B->tpi = tpi;
+  B->fused = fused;
   struct It { double cost; int4 w; };
   std::vector<It> its;
   int max_nj = 16, max_n = 1, max_rbt = 1, max_dress = 1;
@@ -126,7 +131,7 @@ dse_status set_launch(dse_batch* B, int slices, int grid, int order) {
       const int rows = kind == 0 ? v.RZ : v.RG;
       const double c = item_cost(v, kind);
       for (int r = 0; r < rows; ++r)
-        for (int t = 0; t < nt; ++t) its.push_back({c, make_int4(b, kind, r, t)});
+        for (int t = 0; t < nt; t += tpi) its.push_back({c * std::min(tpi, nt - t), make_int4(b, kind, r, t)});
     }
     max_nj = std::max(max_nj, v.NJ);
     max_n = std::max(max_n, v.n);
@@ -161,21 +166,34 @@ dse_status upload_ctl(dse_batch* B) {
   return DSE_OK;
 }
 
+// The staged launches' persistent grid for the fused form's point stage is
+// its own cooperative grid; the residual pass always runs staged (with
+// persistent blocks when the fused form is chosen).
 dse_status eval_residuals(dse_batch* B, const double* cpk, int which) {
   const dse::BatchArgs& a = B->args;
   BHIP_TRY(B, dse::launch_batch_dressing(a, cpk, which, B->d_counter, B->st));
-  BHIP_TRY(B, dse::launch_batch_points(a, B->d_items, B->n_items, 0, B->grid, B->d_counter, B->st));
+  BHIP_TRY(B, dse::launch_batch_points(a, B->d_items, B->n_items, 0, B->grid, B->tpi, B->d_counter, B->st));
   BHIP_TRY(B, dse::launch_batch_residual_rows(a, which, B->st));
   return DSE_OK;
 }
 
 dse_status eval_jacobians(dse_batch* B, const double* cpk) {
   const dse::BatchArgs& a = B->args;
+  if (B->fused) {
+    BHIP_TRY(B, dse::launch_batch_fused(a, cpk, B->d_items, B->n_items, B->tpi, B->grid, B->d_counter, B->st));
+    return DSE_OK;
+  }
   BHIP_TRY(B, dse::launch_batch_dressing(a, cpk, 0, B->d_counter, B->st));
-  BHIP_TRY(B, dse::launch_batch_points(a, B->d_items, B->n_items, 1, B->grid, B->d_counter, B->st));
+  BHIP_TRY(B, dse::launch_batch_points(a, B->d_items, B->n_items, 1, B->grid, B->tpi, B->d_counter, B->st));
   BHIP_TRY(B, dse::launch_batch_contract(a, B->st));
   BHIP_TRY(B, dse::launch_batch_assemble(a, B->st));
   return DSE_OK;
+}
+
+// Largest cooperative grid of the fused form (0: not available).
+int fused_grid(const dse_batch* B) {
+  if (!B->coop) return 0;
+  return dse::batch_fused_occupancy(B->args.max_nj) * B->ncu;
 }
 
 dse_status read_nrm(dse_batch* B, int which, std::vector<double>& out) {
@@ -262,6 +280,8 @@ dse_status dse_batch_init(const dse_params* p, int32_t count, void* d_workspace,
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, B->device) == hipSuccess && ncu > 0)
     B->ncu = ncu;
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, B->device) == hipSuccess) B->coop = coop;
   char* c = B->ws;
   B->d_desc = (dse::SolveDesc*)c; c += al(count * sizeof(dse::SolveDesc));
   B->d_items = (int4*)c; c += al((size_t)s.max_items * sizeof(int4));
@@ -333,24 +353,49 @@ dse_status dse_batch_start_guess(dse_batch* B, double* d_c) {
   return DSE_OK;
 }
 
-dse_status dse_batch_set_launch(dse_batch* B, int32_t slices, int32_t persistent_blocks, int32_t order) {
+dse_status dse_batch_set_launch_ex(dse_batch* B, int32_t slices, int32_t persistent_blocks, int32_t order,
+                                   int32_t tiles_per_item, int32_t fused) {
   if (!B) return DSE_E_INVALID;
   if (slices < 1 || slices > B->ks_cap || (slices & (slices - 1)) || persistent_blocks < 0 ||
-      (order != 0 && order != 1)) {
-    set_err(B->err, "slices must be a power of two in [1, %d], persistent_blocks >= 0, order 0 or 1",
+      (order != 0 && order != 1) || tiles_per_item < 1 || tiles_per_item > 64 || (fused != 0 && fused != 1)) {
+    set_err(B->err,
+            "slices must be a power of two in [1, %d], persistent_blocks >= 0, order 0 or 1, "
+            "tiles_per_item in [1, 64], fused 0 or 1",
             B->ks_cap);
     return DSE_E_INVALID;
   }
   DevGuard dg(B->device);
-  return set_launch(B, slices, persistent_blocks, order);
+  if (fused) {
+    const int cap = fused_grid(B);
+    if (cap < 1) {
+      set_err(B->err, "the device offers no cooperative launch for the fused assembly");
+      return DSE_E_INVALID;
+    }
+    if (persistent_blocks < 1 || persistent_blocks > cap) {
+      set_err(B->err, "fused: persistent_blocks must be in [1, %d] (all resident)", cap);
+      return DSE_E_INVALID;
+    }
+  }
+  return set_launch(B, slices, persistent_blocks, order, tiles_per_item, fused);
 }
 
-dse_status dse_batch_get_launch(const dse_batch* B, int32_t* slices, int32_t* persistent_blocks, int32_t* order) {
+dse_status dse_batch_set_launch(dse_batch* B, int32_t slices, int32_t persistent_blocks, int32_t order) {
+  return dse_batch_set_launch_ex(B, slices, persistent_blocks, order, 1, 0);
+}
+
+dse_status dse_batch_get_launch_ex(const dse_batch* B, int32_t* slices, int32_t* persistent_blocks, int32_t* order,
+                                   int32_t* tiles_per_item, int32_t* fused) {
   if (!B) return DSE_E_INVALID;
   if (slices) *slices = B->slices;
   if (persistent_blocks) *persistent_blocks = B->grid;
   if (order) *order = B->order;
+  if (tiles_per_item) *tiles_per_item = B->tpi;
+  if (fused) *fused = B->fused;
   return DSE_OK;
+}
+
+dse_status dse_batch_get_launch(const dse_batch* B, int32_t* slices, int32_t* persistent_blocks, int32_t* order) {
+  return dse_batch_get_launch_ex(B, slices, persistent_blocks, order, nullptr, nullptr);
 }
 
 dse_status dse_batch_jacobian(dse_batch* B, const double* d_c, double* d_J, double* d_F) {
@@ -378,43 +423,54 @@ dse_status dse_batch_autotune(dse_batch* B, const double* d_c, dse_batch_tuning*
   dse_batch_tuning r;
   memset(&r, 0, sizeof(r));
   double best = INFINITY;
-  int bs = 1, bg = 0, bo = 1;
+  int bs = 1, bg = 0, bo = 1, bt = 1, bf = 0;
   const int occ = dse::batch_points_occupancy(1, B->args.max_nj);
-  for (int ks = 1; ks <= B->ks_cap; ks *= 2)
-    for (int pers = 0; pers < 2; ++pers)
-      for (int ord = 1; ord >= 0; --ord) {
-        const int grid = pers ? occ * B->ncu : 0;
-        if ((s = set_launch(B, ks, grid, ord)) != DSE_OK) break;
-        double ms_best = INFINITY;
-        for (int rep_ = 0; rep_ < 4 && s == DSE_OK; ++rep_) {
-          if (hipEventRecord(e0, B->st) != hipSuccess) { s = DSE_E_DEVICE; break; }
-          if ((s = eval_jacobians(B, d_c)) != DSE_OK) break;
-          if (hipEventRecord(e1, B->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            s = DSE_E_DEVICE;
-            break;
-          }
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          if (rep_ > 0) ms_best = std::min(ms_best, (double)ms);  // the first run is a warm-up
-        }
-        if (s != DSE_OK) break;
-        if (r.n_candidates < 32) {
-          const int i = r.n_candidates++;
-          r.cand_slices[i] = ks;
-          r.cand_blocks[i] = grid;
-          r.cand_order[i] = ord;
-          r.cand_ms[i] = ms_best;
-        }
-        if (ms_best < best) { best = ms_best; bs = ks; bg = grid; bo = ord; }
-      }
+  const int fgrid = fused_grid(B);
+  // one candidate: the best of three timed assemblies after a warm-up
+  auto time_one = [&](int ks, int grid, int ord, int tpi, int fu) -> dse_status {
+    dse_status st = set_launch(B, ks, grid, ord, tpi, fu);
+    if (st != DSE_OK) return st;
+    double ms_best = INFINITY;
+    for (int rep_ = 0; rep_ < 4; ++rep_) {
+      if (hipEventRecord(e0, B->st) != hipSuccess) return DSE_E_DEVICE;
+      if ((st = eval_jacobians(B, d_c)) != DSE_OK) return st;
+      if (hipEventRecord(e1, B->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return DSE_E_DEVICE;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep_ > 0) ms_best = std::min(ms_best, (double)ms);  // the first run is a warm-up
+    }
+    if (r.n_candidates < 32) {
+      const int i = r.n_candidates++;
+      r.cand_slices[i] = ks;
+      r.cand_blocks[i] = grid;
+      r.cand_order[i] = ord;
+      r.cand_ms[i] = ms_best;
+      r.cand_tiles[i] = tpi;
+      r.cand_fused[i] = fu;
+    }
+    if (ms_best < best) { best = ms_best; bs = ks; bg = grid; bo = ord; bt = tpi; bf = fu; }
+    return DSE_OK;
+  };
+  // angular slices x launch form (one workgroup per item, persistent
+  // workgroups, the fused cooperative launch) x partial tiles per item, queue
+  // largest first; then problem order for the best of them
+  for (int ks = 1; ks <= B->ks_cap && s == DSE_OK; ks *= 2)
+    for (int form = 0; form < 3 && s == DSE_OK; ++form) {
+      if (form == 2 && fgrid < 1) continue;
+      const int grid = form == 0 ? 0 : (form == 1 ? occ * B->ncu : fgrid);
+      for (int tpi = 1; tpi <= 4 && s == DSE_OK; tpi *= 2) s = time_one(ks, grid, 1, tpi, form == 2 ? 1 : 0);
+    }
+  if (s == DSE_OK) s = time_one(bs, bg, 0, bt, bf);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != DSE_OK) { set_err(B->err, "autotune: evaluation failed"); return s; }
-  s = set_launch(B, bs, bg, bo);
+  s = set_launch(B, bs, bg, bo, bt, bf);
   r.slices = bs;
   r.persistent_blocks = bg;
   r.order = bo;
   r.best_ms = best;
+  r.tiles_per_item = bt;
+  r.fused = bf;
   if (rep) *rep = r;
   return s;
 }

@@ -177,12 +177,19 @@ struct BatchArgs {
 };
 hipError_t launch_batch_dressing(const BatchArgs& a, const double* cpk, int which, int* counter,
                                  hipStream_t st);
-// items: (problem, kind, row, tile), in queue order.  grid = 0: one block per
-// item in queue order; grid > 0: that many persistent blocks take items from
-// the queue through the counter (which the dressing launch resets).
-hipError_t launch_batch_points(const BatchArgs& a, const int4* items, int n_items, int mode, int grid,
+// items: (problem, kind, row, first tile), in queue order; each item takes
+// tpi consecutive partial tiles of its row.  grid = 0: one block per item in
+// queue order; grid > 0: that many persistent blocks take items from the
+// queue through the counter (which the dressing launch resets).
+hipError_t launch_batch_points(const BatchArgs& a, const int4* items, int n_items, int mode, int grid, int tpi,
                                int* counter, hipStream_t st);
 int batch_points_occupancy(int mode, int max_nj);  // resident blocks per CU
+// The whole Newton-matrix assembly (dressings, points, contraction, rows) in
+// one cooperative launch of grid resident blocks (at most the occupancy of
+// batch_fused_occupancy times the CUs).
+hipError_t launch_batch_fused(const BatchArgs& a, const double* cpk, const int4* items, int n_items, int tpi,
+                              int grid, int* counter, hipStream_t st);
+int batch_fused_occupancy(int max_nj);  // resident blocks per CU (0: not available)
 hipError_t launch_batch_contract(const BatchArgs& a, hipStream_t st);
 hipError_t launch_batch_assemble(const BatchArgs& a, hipStream_t st);
 hipError_t launch_batch_residual_rows(const BatchArgs& a, int which, hipStream_t st);

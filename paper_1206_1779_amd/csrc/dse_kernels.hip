@@ -20,6 +20,7 @@
 //
 // Determinism: every sum runs in a fixed order; no floating-point atomics.
 
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -1840,14 +1841,45 @@ __global__ __launch_bounds__(256) void batch_dressing_kernel(const SolveDesc* __
   dressing_body(sd.v, sd.ph, which ? sd.v.ct : cpk + sd.coff, blockIdx.x * 256, gridDim.x * 256, blockIdx.x == 0);
 }
 
-// Queue of (problem, kind, row, tile) items, largest first.  The kernel is
-// instantiated for the family's largest padded order and holds a body for
-// every order up to it.
+// One queue item: (problem, kind, row, first tile); the item takes tpi
+// consecutive partial tiles of the row (each writes its own partial sums).
+// The body is instantiated for every order up to NJMAX.
+template <int MODE, int NJMAX>
+__device__ __forceinline__ void batch_item(const SolveDesc* __restrict__ d, const int* __restrict__ mask,
+                                           const int4 w, int tpi, double* smem) {
+  const int b = uniform(w.x);
+  if (!mask[b]) return;
+  const SolveDesc& sd = d[b];
+  const int kind = uniform(w.y), row = uniform(w.z), t0 = uniform(w.w);
+  const int nj = uniform(sd.v.NJ);
+  const int nt = sd.v.nqt * sd.v.KS;
+  for (int tile = t0; tile < t0 + tpi && tile < nt; ++tile) {
+    if (tile > t0) __syncthreads();  // the LDS is reused
+#define DSE_BATCH_CASE(N)                                                                   \
+  if constexpr (N <= NJMAX) {                                                               \
+    if (nj == N) {                                                                          \
+      if (kind == GLUON) point_body<GLUON, N, MODE, false, true>(sd.v, sd.ph, row, tile, smem); \
+      else point_body<GHOST, N, MODE, false, true>(sd.v, sd.ph, row, tile, smem);           \
+    }                                                                                       \
+  }
+    DSE_BATCH_CASE(16)
+    DSE_BATCH_CASE(32)
+    DSE_BATCH_CASE(48)
+    DSE_BATCH_CASE(64)
+    DSE_BATCH_CASE(96)
+    DSE_BATCH_CASE(128)
+#undef DSE_BATCH_CASE
+  }
+}
+
+// Queue of (problem, kind, row, tile) items, largest first: one workgroup per
+// item in queue order, or persistent workgroups taking items through the
+// counter.
 template <int MODE, int NJMAX>
 __global__ __launch_bounds__(256) void batch_point_kernel(const SolveDesc* __restrict__ d,
                                                           const int* __restrict__ mask,
                                                           const int4* __restrict__ items, int n_items,
-                                                          int* counter, int persistent) {
+                                                          int* counter, int persistent, int tpi) {
   __shared__ double smem[point_smem<NJMAX, true>()];
   __shared__ int s_item;
   int it = blockIdx.x;
@@ -1858,27 +1890,7 @@ __global__ __launch_bounds__(256) void batch_point_kernel(const SolveDesc* __res
       it = uniform(s_item);
     }
     if (it >= n_items) break;
-    const int4 w = items[it];
-    const int b = uniform(w.x);
-    if (mask[b]) {
-      const SolveDesc& sd = d[b];
-      const int kind = uniform(w.y), row = uniform(w.z), tile = uniform(w.w);
-      const int nj = uniform(sd.v.NJ);
-#define DSE_BATCH_CASE(N)                                                                   \
-  if constexpr (N <= NJMAX) {                                                               \
-    if (nj == N) {                                                                          \
-      if (kind == GLUON) point_body<GLUON, N, MODE, false, true>(sd.v, sd.ph, row, tile, smem); \
-      else point_body<GHOST, N, MODE, false, true>(sd.v, sd.ph, row, tile, smem);           \
-    }                                                                                       \
-  }
-      DSE_BATCH_CASE(16)
-      DSE_BATCH_CASE(32)
-      DSE_BATCH_CASE(48)
-      DSE_BATCH_CASE(64)
-      DSE_BATCH_CASE(96)
-      DSE_BATCH_CASE(128)
-#undef DSE_BATCH_CASE
-    }
+    batch_item<MODE, NJMAX>(d, mask, items[it], tpi, smem);
     if (!persistent) break;
     __syncthreads();  // the next item reuses s_item and the LDS
   }
@@ -1901,6 +1913,71 @@ __global__ __launch_bounds__(256) void batch_assemble_kernel(const SolveDesc* __
   const SolveDesc& sd = d[b];
   if ((int)blockIdx.x >= sd.v.n) return;
   assemble_body<false>(sd.v, sd.ph, blockIdx.x, sd.v.J, sd.v.F, sd.v.S);
+}
+
+// The family's Newton-matrix assembly in one cooperative launch of resident
+// workgroups: the dressings of every problem, the point items through the
+// queue, the contraction tiles, the assembly rows.  Each stage is dealt over
+// the grid and separated from the next by a grid-wide barrier (the
+// cooperative launch guarantees that every workgroup is resident, so the
+// barrier completes); the units of every stage are those of the staged
+// launches, so the results are bit-identical to them.
+template <int NJMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_fused_kernel(
+    BatchArgs a, const double* __restrict__ cpk, const int4* __restrict__ items, int n_items, int tpi,
+    int* counter) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  __shared__ double smem[point_smem<NJMAX, true>()];
+  __shared__ int s_item;
+  const SolveDesc* __restrict__ d = a.desc;
+  const int nb = gridDim.x;
+  // dressings: (problem, block) units
+  const int ndu = a.count * a.max_dress_blocks;
+  for (int u = blockIdx.x; u < ndu; u += nb) {
+    const int b = u / a.max_dress_blocks, blk = u - b * a.max_dress_blocks;
+    if (a.mask[b]) {
+      const SolveDesc& sd = d[b];
+      dressing_body(sd.v, sd.ph, cpk + sd.coff, blk * 256, a.max_dress_blocks * 256, blk == 0);
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+  grid.sync();
+  // point items through the queue
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = uniform(s_item);
+    if (it >= n_items) break;
+    batch_item<MODE_JAC, NJMAX>(d, a.mask, items[it], tpi, smem);
+    __syncthreads();
+  }
+  grid.sync();
+  // contraction tiles: (problem, row block, part, column block) units
+  const int nct = a.max_nj / 16, per = a.max_rbt * kCS * nct;
+  for (int u = blockIdx.x; u < a.count * per; u += nb) {
+    const int b = u / per;
+    int r = u - b * per;
+    const int bx = r / (kCS * nct);
+    r -= bx * (kCS * nct);
+    const int part = r / nct, by = r - part * nct;
+    if (a.mask[b]) {
+      const Views& v = d[b].v;
+      if (bx < v.Rbp / 16 + (v.RG + 15) / 16 && by < v.NJ / 16) contract_body<false>(v, bx, by, part);
+    }
+    __syncthreads();
+  }
+  grid.sync();
+  // assembly rows
+  for (int u = blockIdx.x; u < a.count * a.max_n; u += nb) {
+    const int b = u / a.max_n, row = u - b * a.max_n;
+    if (a.mask[b]) {
+      const SolveDesc& sd = d[b];
+      if (row < sd.v.n) assemble_body<false>(sd.v, sd.ph, row, sd.v.J, sd.v.F, sd.v.S);
+    }
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(256) void batch_residual_rows_kernel(const SolveDesc* __restrict__ d,
@@ -2173,36 +2250,70 @@ hipError_t launch_batch_dressing(const BatchArgs& a, const double* cpk, int whic
 }
 
 template <int MODE, int NJMAX>
-static hipError_t batch_points_nj(const BatchArgs& a, const int4* items, int n_items, int grid, int* counter,
-                                  hipStream_t st) {
+static hipError_t batch_points_nj(const BatchArgs& a, const int4* items, int n_items, int grid, int tpi,
+                                  int* counter, hipStream_t st) {
   const int blocks = grid > 0 ? grid : n_items;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL((batch_point_kernel<MODE, NJMAX>), dim3(blocks), dim3(256), 0, st, a.desc, a.mask, items,
-                     n_items, counter, grid > 0 ? 1 : 0);
+                     n_items, counter, grid > 0 ? 1 : 0, tpi);
   return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t batch_points_mode(const BatchArgs& a, const int4* items, int n_items, int grid, int* counter,
-                                    hipStream_t st) {
+static hipError_t batch_points_mode(const BatchArgs& a, const int4* items, int n_items, int grid, int tpi,
+                                    int* counter, hipStream_t st) {
   switch (a.max_nj) {
-    case 16: return batch_points_nj<MODE, 16>(a, items, n_items, grid, counter, st);
-    case 32: return batch_points_nj<MODE, 32>(a, items, n_items, grid, counter, st);
-    case 48: return batch_points_nj<MODE, 48>(a, items, n_items, grid, counter, st);
-    case 64: return batch_points_nj<MODE, 64>(a, items, n_items, grid, counter, st);
-    case 96: return batch_points_nj<MODE, 96>(a, items, n_items, grid, counter, st);
-    case 128: return batch_points_nj<MODE, 128>(a, items, n_items, grid, counter, st);
+    case 16: return batch_points_nj<MODE, 16>(a, items, n_items, grid, tpi, counter, st);
+    case 32: return batch_points_nj<MODE, 32>(a, items, n_items, grid, tpi, counter, st);
+    case 48: return batch_points_nj<MODE, 48>(a, items, n_items, grid, tpi, counter, st);
+    case 64: return batch_points_nj<MODE, 64>(a, items, n_items, grid, tpi, counter, st);
+    case 96: return batch_points_nj<MODE, 96>(a, items, n_items, grid, tpi, counter, st);
+    case 128: return batch_points_nj<MODE, 128>(a, items, n_items, grid, tpi, counter, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_batch_points(const BatchArgs& a, const int4* items, int n_items, int mode, int grid,
+hipError_t launch_batch_points(const BatchArgs& a, const int4* items, int n_items, int mode, int grid, int tpi,
                                int* counter, hipStream_t st) {
+  if (tpi < 1) return hipErrorInvalidValue;
   switch (mode) {
-    case MODE_RES: return batch_points_mode<MODE_RES>(a, items, n_items, grid, counter, st);
-    case MODE_JAC: return batch_points_mode<MODE_JAC>(a, items, n_items, grid, counter, st);
+    case MODE_RES: return batch_points_mode<MODE_RES>(a, items, n_items, grid, tpi, counter, st);
+    case MODE_JAC: return batch_points_mode<MODE_JAC>(a, items, n_items, grid, tpi, counter, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int NJMAX>
+static const void* fused_fn() {
+  return reinterpret_cast<const void*>(&batch_fused_kernel<NJMAX>);
+}
+
+static const void* fused_kernel_for(int max_nj) {
+  switch (max_nj) {
+    case 16: return fused_fn<16>();
+    case 32: return fused_fn<32>();
+    case 48: return fused_fn<48>();
+    case 64: return fused_fn<64>();
+    case 96: return fused_fn<96>();
+    case 128: return fused_fn<128>();
+    default: return nullptr;
+  }
+}
+
+int batch_fused_occupancy(int max_nj) {
+  const void* f = fused_kernel_for(max_nj);
+  int nb = 0;
+  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_batch_fused(const BatchArgs& a, const double* cpk, const int4* items, int n_items, int tpi,
+                              int grid, int* counter, hipStream_t st) {
+  const void* f = fused_kernel_for(a.max_nj);
+  if (!f || grid < 1 || tpi < 1) return hipErrorInvalidValue;
+  BatchArgs aa = a;
+  void* args[] = {&aa, (void*)&cpk, (void*)&items, &n_items, &tpi, &counter};
+  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(256), args, 0, st);
 }
 
 template <int MODE, int NJMAX>

@@ -16,7 +16,7 @@ import torch  # loads the HIP runtime that libdse.so binds to
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdse.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_N = 128
 QUAD_TANH_SINH = 1  # dse_params.quad bits (include/dse.h)
 QUAD_SPLIT = 2
@@ -31,7 +31,8 @@ EXPORTS = [
     "dse_set_physics", "dse_newton_step", "dse_set_graphs",
     "dse_batch_workspace_bytes", "dse_batch_init", "dse_batch_destroy", "dse_batch_last_error",
     "dse_batch_offsets", "dse_batch_start_guess", "dse_batch_jacobian", "dse_batch_newton_solve",
-    "dse_batch_autotune", "dse_batch_set_launch", "dse_batch_get_launch", "dse_lu_solve_noalloc",
+    "dse_batch_autotune", "dse_batch_set_launch", "dse_batch_get_launch",
+    "dse_batch_set_launch_ex", "dse_batch_get_launch_ex", "dse_lu_solve_noalloc",
     "dse_renorm_scale", "dse_gauss_legendre_workspace_bytes", "dse_gauss_legendre",
     "dse_schwinger_workspace_bytes", "dse_schwinger",
 ]
@@ -67,7 +68,9 @@ class BatchTuning(C.Structure):
     _fields_ = [("slices", C.c_int32), ("persistent_blocks", C.c_int32), ("order", C.c_int32),
                 ("n_candidates", C.c_int32), ("best_ms", C.c_double),
                 ("cand_slices", C.c_int32 * 32), ("cand_blocks", C.c_int32 * 32),
-                ("cand_order", C.c_int32 * 32), ("cand_ms", C.c_double * 32)]
+                ("cand_order", C.c_int32 * 32), ("cand_ms", C.c_double * 32),
+                ("tiles_per_item", C.c_int32), ("fused", C.c_int32),
+                ("cand_tiles", C.c_int32 * 32), ("cand_fused", C.c_int32 * 32)]
 
 
 class DSEError(RuntimeError):
@@ -126,6 +129,8 @@ def load():
             "dse_batch_newton_solve": (C.c_int, [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonReport)]),
             "dse_batch_autotune": (C.c_int, [vp, vp, C.POINTER(BatchTuning)]),
             "dse_batch_set_launch": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
+            "dse_batch_set_launch_ex": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+            "dse_batch_get_launch_ex": (C.c_int, [vp] + [C.POINTER(C.c_int32)] * 5),
             "dse_batch_get_launch": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                                C.POINTER(C.c_int32)]),
         }
@@ -550,15 +555,21 @@ class Batch:
         with torch.cuda.device(self.device):
             self._check(self.lib.dse_batch_autotune(self.h, _ptr(c), C.byref(r)))
         cands = [dict(slices=r.cand_slices[i], persistent_blocks=r.cand_blocks[i],
-                      order=r.cand_order[i], ms=r.cand_ms[i]) for i in range(r.n_candidates)]
+                      order=r.cand_order[i], tiles_per_item=r.cand_tiles[i], fused=r.cand_fused[i],
+                      ms=r.cand_ms[i]) for i in range(r.n_candidates)]
         return dict(slices=r.slices, persistent_blocks=r.persistent_blocks, order=r.order,
-                    best_ms=r.best_ms, candidates=cands)
+                    tiles_per_item=r.tiles_per_item, fused=r.fused, best_ms=r.best_ms, candidates=cands)
 
-    def set_launch(self, slices=1, persistent_blocks=0, order=1):
+    def set_launch(self, slices=1, persistent_blocks=0, order=1, tiles_per_item=1, fused=0):
         with torch.cuda.device(self.device):
-            self._check(self.lib.dse_batch_set_launch(self.h, slices, persistent_blocks, order))
+            self._check(self.lib.dse_batch_set_launch_ex(self.h, slices, persistent_blocks, order,
+                                                         tiles_per_item, fused))
 
-    def get_launch(self):
-        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        self._check(self.lib.dse_batch_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c)))
-        return dict(slices=a.value, persistent_blocks=b.value, order=c.value)
+    def get_launch(self, full: bool = False):
+        a, b, c, d, e = (C.c_int32() for _ in range(5))
+        self._check(self.lib.dse_batch_get_launch_ex(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d),
+                                                     C.byref(e)))
+        out = dict(slices=a.value, persistent_blocks=b.value, order=c.value)
+        if full:
+            out.update(tiles_per_item=d.value, fused=e.value)
+        return out

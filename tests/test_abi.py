@@ -42,7 +42,7 @@ def test_binding_covers_header():
 def test_defaults_and_sizes(lib):
     from paper_1206_1779_amd import dse
     p = dse.params()
-    assert p.abi_version == 1 and p.n_z == 16 and abs(p.kappa - 0.5953525826) < 1e-9
+    assert p.abi_version == 2 and p.n_z == 16 and abs(p.kappa - 0.5953525826) < 1e-9
     assert p.delta == -9 / 44 and p.gamma == -13 / 22
     n1 = lib.dse_workspace_bytes(C.byref(p))
     p2 = dse.params(n_z=64, n_g=64, n_rad=256, n_ir=64, n_ang=64)

@@ -90,6 +90,51 @@ def test_batch_jacobian_every_launch_form(ref, dse):
                     _check_JF(ref, cfg, cs[i], Ji, Fi)
 
 
+def test_batch_fused_launch_and_tile_groups(ref, dse):
+    """The fused cooperative assembly (dressings, points, contraction, rows in
+    one launch with grid-wide barriers) and items of 2 or 4 partial tiles give
+    the same J and F bit for bit as the staged launches with one tile per
+    item, for every angular split; the fused form solves the family like the
+    staged one."""
+    cfgs = _small()
+    b = dse.Batch(cfgs)
+    c0 = b.start_guess()
+    pert = np.concatenate([workloads.perturbation(d["n_z"], d["n_g"], 0.03, seed=50 + i)
+                           for i, d in enumerate(cfgs)])
+    c = _np(c0) + pert
+    for slices in (1, 2, 4):
+        b.set_launch(slices, 0, 1)
+        J0, F0 = (_np(t) for t in b.jacobian(c))
+        for blocks, tpi, fused in ((0, 2, 0), (0, 4, 0), (29, 2, 0), (16, 1, 1), (16, 4, 1), (3, 2, 1)):
+            _note("launch slices=%d blocks=%d tiles=%d fused=%d" % (slices, blocks, tpi, fused))
+            b.set_launch(slices, blocks, 1, tiles_per_item=tpi, fused=fused)
+            assert b.get_launch(full=True) == dict(slices=slices, persistent_blocks=blocks, order=1,
+                                                   tiles_per_item=tpi, fused=fused)
+            J, F = (_np(t) for t in b.jacobian(c))
+            assert np.array_equal(J, J0) and np.array_equal(F, F0)
+    b.set_launch(2, 0, 1)
+    cs, rs = b.newton(c0)
+    b.set_launch(2, 16, 1, tiles_per_item=2, fused=1)
+    cf, rf = b.newton(c0)
+    assert all(r.status == 0 for r in rf)
+    assert [r.iters for r in rf] == [r.iters for r in rs]
+    assert np.array_equal(_np(cf), _np(cs))
+
+
+def test_batch_launch_rejections(dse):
+    b = dse.Batch(_small())
+    for kw in (dict(tiles_per_item=0), dict(tiles_per_item=65), dict(fused=2)):
+        with pytest.raises(dse.DSEError) as e:
+            b.set_launch(1, 0, 1, **kw)
+        assert e.value.status == 1
+    with pytest.raises(dse.DSEError) as e:
+        b.set_launch(1, 0, 1, fused=1)  # the fused form needs its resident grid
+    assert e.value.status == 1
+    with pytest.raises(dse.DSEError) as e:
+        b.set_launch(1, 1 << 30, 1, fused=1)
+    assert e.value.status == 1 and "persistent_blocks" in str(e.value)
+
+
 def test_batch_matches_single_problem_path(dse):
     cfgs = _small()
     b = dse.Batch(cfgs)
