@@ -273,6 +273,34 @@ def bench_coupling(dse, workloads, torch) -> dict:
             "g0_inv": cfg["g0_inv"]}
 
 
+def bench_lu(dse, workloads, torch, reps: int = 50) -> dict:
+    """The device LU alone (dse_lu_solve: row maxima, factorisation with
+    partial pivoting, solve) at the Newton orders n = 128 (N = 64) and 256
+    (N = 128) on seeded Gaussian matrices with a shifted diagonal; wall time
+    per call including its synchronisation, and the solution's residual."""
+    import numpy as np
+    out = {}
+    for n in (128, 256):
+        s = dse.Solver(**workloads.config("cfg1", n_z=n // 2, n_g=n - n // 2))
+        rng = np.random.default_rng(n)
+        A = rng.standard_normal((n, n)) + np.diag(rng.uniform(-3, 3, n))
+        b = rng.standard_normal(n)
+        Ad = torch.tensor(A, device="cuda:0")
+        bd = torch.tensor(b, device="cuda:0")
+        for _ in range(3):
+            x = s.lu_solve(Ad, bd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x = s.lu_solve(Ad, bd)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        xn = x.cpu().numpy()
+        out["n%d" % n] = {"ms_per_call": dt * 1e3,
+                          "rel_residual": float(np.linalg.norm(A @ xn - b) / (np.linalg.norm(A) * np.linalg.norm(xn)))}
+    return out
+
+
 def bench_schwinger(dse, workloads, torch, with_cpu: bool = True) -> dict:
     """The Schwinger function of the gluon propagator (Sec. 2.2; the paper's
     second workload, Table 2): the scaling solution at the paper's parameters
@@ -425,6 +453,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, mixed and finite-difference comparisons")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device five times (reference for HBM counters)")
+    ap.add_argument("--leg", choices=["schwinger", "lu", "batched"], default=None,
+                    help="run one secondary leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and has no "
@@ -444,6 +474,12 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "launches": 5}), flush=True)
+        return 0
+    if args.leg:
+        legs = {"schwinger": lambda: bench_schwinger(dse, workloads, torch, with_cpu=False),
+                "lu": lambda: bench_lu(dse, workloads, torch),
+                "batched": lambda: bench_batched(dse, workloads, torch)}
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return 0
     name = "cfg2"
     cfg = workloads.config(name)
@@ -540,6 +576,7 @@ def main() -> int:
         out["coupling"] = bench_coupling(dse, workloads, torch)
         out["root_parity"] = bench_root_parity(dse, workloads, torch)
         out["schwinger"] = bench_schwinger(dse, workloads, torch, with_cpu=not args.no_cpu)
+        out["lu"] = bench_lu(dse, workloads, torch)
         out["discretisation"] = bench_discretisation(dse, workloads, torch)
     if not args.no_cpu:
         cb = cpu_baseline(cfg, c.cpu().numpy())
