@@ -483,7 +483,11 @@ def main() -> int:
         return 0
     name = "cfg2"
     cfg = workloads.config(name)
-    s = dse.Solver(device="cuda:0", **cfg)
+    # the solver's own stream (not the legacy default stream), as a serving
+    # loop would use; every tensor operation below is ordered on it
+    stream = torch.cuda.Stream(device="cuda:0")
+    torch.cuda.set_stream(stream)
+    s = dse.Solver(device="cuda:0", stream=stream, **cfg)
     n = s.n
     # the steps run at the solution (the work per step does not depend on c)
     root = s.newton(tol=1e-10).c
@@ -497,16 +501,23 @@ def main() -> int:
         src, dst = bufs[k % 2], bufs[(k + 1) % 2]
         s.newton_step(src, 1.0, out=(dst, F_out, S_out))
 
-    # timed region: K steps replayed from the library's recorded graphs
-    s.set_graphs(True)
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        step(k)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    def timed_steps(graphs: bool) -> float:
+        s.set_graphs(graphs)
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            step(k)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # the step replayed from the library's recorded graphs, then the timed
+    # region: K steps with the library's default launches (kernel by kernel,
+    # the faster form here: a graph launch adds a gap of about 8 us before
+    # its first kernel)
+    dt_graph = timed_steps(True)
+    dt = timed_steps(False)
     ms_step = dt / args.steps * 1e3
     value = n * n / (dt / args.steps)
     # the same K steps launched one by one, with HIP events around every stage
@@ -521,7 +532,7 @@ def main() -> int:
     dt_eager = time.perf_counter() - t0
     stages, cnt = s.read_timings()
     s.set_timing(False)
-    s.set_graphs(True)
+    s.set_graphs(False)
     c = s.start_guess()
 
     # Jacobian assembly alone (device time of its five stages)
@@ -559,8 +570,10 @@ def main() -> int:
         "config": {"workload": workloads.WORKLOAD_NAMES[name], "n_z": cfg["n_z"], "n_g": cfg["n_g"],
                    "n_rad": cfg["n_rad"], "n_ir": cfg["n_ir"], "n_ang": cfg["n_ang"],
                    "g0": 1.0 / cfg["g0_inv"],
-                   "step": "LU solve of the held Newton matrix, update, J+F assembly at the new point"},
-        "ms_per_step_without_graph": dt_eager / args.steps * 1e3,
+                   "step": "LU solve of the held Newton matrix, update, J+F assembly at the new point",
+                   "launch": "kernel by kernel on the solver's stream"},
+        "ms_per_step_graph_replay": dt_graph / args.steps * 1e3,
+        "ms_per_step_with_stage_events": dt_eager / args.steps * 1e3,
         "assembly_entries_per_s": n * n / t_asm,
         "assembly_ms": t_asm * 1e3,
         "stage_ms": dict(zip(["dressing", "gluon_points", "ghost_points", "contract", "assemble"], stages)),

@@ -228,7 +228,7 @@ struct dse_ctx {
   // recorded Newton steps (dse_newton_step): the launch sequence for one set
   // of pointers, relaxation and kind (with or without the assembly at d_c),
   // replayed as a HIP graph; a few are kept (alternating buffers need two)
-  bool graphs = true;
+  bool graphs = false;
   hipStream_t cap_st = nullptr;  // private stream the graphs are recorded on (the
                                  // caller's stream may be the null stream, which
                                  // cannot be captured); replays go to st
