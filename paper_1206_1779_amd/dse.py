@@ -392,8 +392,9 @@ class Solver:
 
     def newton_step(self, c, rho: float = 1.0, out=None, check: bool = False):
         """One Newton iteration: returns (c_new, F(c_new), S(c_new)).  `out`
-        (optional) is a tuple of three preallocated vectors; reusing the same
-        ones lets the library replay its recorded graph."""
+        (optional) is a tuple of three preallocated vectors; with graph replay
+        switched on (set_graphs) reusing the same ones lets the library replay
+        its recorded graph."""
         c = self._vec(c)
         cn, F, S = out if out is not None else (self._vec(), self._vec(), self._vec())
         with torch.cuda.device(self.device):
@@ -402,6 +403,7 @@ class Solver:
         return cn, F, S
 
     def set_graphs(self, on: bool = True):
+        """Graph replay of newton_step (off by default: kernel by kernel is faster)."""
         self._check(self.lib.dse_set_graphs(self.h, 1 if on else 0))
 
     def vjp(self, c, u, with_c: bool = True):
