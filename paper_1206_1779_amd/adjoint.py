@@ -13,8 +13,6 @@ from __future__ import annotations
 
 import torch
 
-from . import dse as _dse
-
 
 class ImplicitSolve(torch.autograd.Function):
     """c* = ImplicitSolve.apply(theta, solver, c0, newton_kwargs).
