@@ -117,6 +117,36 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// v of lane (lane ^ r) for a constant r (the switch folds once r is known):
+// partners inside a quad of lanes by a DPP quad permutation (vector moves,
+// no LDS round trip and no address operand), others by ds_bpermute.
+template <int CTRL>
+__device__ __forceinline__ int quad_perm_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_perm_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = quad_perm_i<CTRL>((int)(b & 0xffffffffLL)), hi = quad_perm_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_xor(double v, int r) {
+  switch (r) {
+    case 1: return quad_perm_d<0xB1>(v);  // quad_perm [1,0,3,2]
+    case 2: return quad_perm_d<0x4E>(v);  // [2,3,0,1]
+    case 3: return quad_perm_d<0x1B>(v);  // [3,2,1,0]
+    default: return __shfl_xor(v, r, 64);
+  }
+}
+__device__ __forceinline__ float lane_xor(float v, int r) {
+  switch (r) {
+    case 1: return __int_as_float(quad_perm_i<0xB1>(__float_as_int(v)));
+    case 2: return __int_as_float(quad_perm_i<0x4E>(__float_as_int(v)));
+    case 3: return __int_as_float(quad_perm_i<0x1B>(__float_as_int(v)));
+    default: return __shfl_xor(v, r, 64);
+  }
+}
+
 // --------------------------------------------------------------------------
 // dressing: coef (c_0 halved, zero padded), ln Z / ln G at radial nodes and at
 // the collocation points.
@@ -486,13 +516,13 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
           double sp = stp[0], sc = stc[0];
 #pragma unroll
           for (int m = 1; m < G; ++m) if (want == m) { sp = stp[m]; sc = stc[m]; }
-          tp = __shfl_xor((acc_t)sp, r, 64);
-          tc = __shfl_xor((acc_t)sc, r, 64);
-          pa = __shfl_xor(PaA, r, 64);
-          pb = NT == 2 ? __shfl_xor(PbA, r, 64) : (acc_t)0;
+          tp = lane_xor((acc_t)sp, r);
+          tc = lane_xor((acc_t)sc, r);
+          pa = lane_xor(PaA, r);
+          pb = NT == 2 ? lane_xor(PbA, r) : (acc_t)0;
         }
         // the owner's mapped momentum drives its recurrence
-        const acc_t sr = r == 0 ? sA : __shfl_xor(sA, r, 64);
+        const acc_t sr = r == 0 ? sA : lane_xor(sA, r);
         const acc_t sr2 = sr + sr;
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj) {
@@ -541,12 +571,12 @@ __device__ __forceinline__ void point_body(const Views& v, const Phys& ph, int r
         double sp = qtp[0], sc = qtc[0];
 #pragma unroll
         for (int m = 1; m < G; ++m) if (want == m) { sp = qtp[m]; sc = qtc[m]; }
-        tp = __shfl_xor(sp, r, 64);
-        tc = __shfl_xor(sc, r, 64);
-        pa = KIND == GLUON ? __shfl_xor((double)Ba, r, 64) : 0.0;
-        pb = __shfl_xor((double)Bb, r, 64);
+        tp = lane_xor(sp, r);
+        tc = lane_xor(sc, r);
+        pa = KIND == GLUON ? lane_xor((double)Ba, r) : 0.0;
+        pb = lane_xor((double)Bb, r);
       }
-      const double sr = r == 0 ? sy : __shfl_xor(sy, r, 64);
+      const double sr = r == 0 ? sy : lane_xor(sy, r);
       const double sr2 = sr + sr;
 #pragma unroll
       for (int jj = 0; jj < JT; ++jj) {
