@@ -691,7 +691,7 @@ void point_kernel(Views v, Phys ph) {
 template <bool MIX, bool SPLIT = false>
 __device__ __forceinline__ void contract_body(const Views& v, int bx, int by, int part) {
   using acc_t = typename std::conditional<MIX, float, double>::type;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int Qp = v.Qp, NJ = v.NJ;
   const int ntile = v.nqt * v.KS;
   const int tlo = part * ntile / kCS, thi = (part + 1) * ntile / kCS;
@@ -1328,15 +1328,24 @@ __device__ __forceinline__ void lu_factor_panel(double* M, int ld, int np, const
   for (int m = 0; m < R; ++m) {
     const int pos = k0 + lane + 64 * m;
     lp_[m] = pos < np ? pos : -1;  // -1: no row (never a candidate, never updated)
+    // loads from clamped (in-bounds) addresses, then selects: no load waits
+    // inside a divergent branch
     if (FIRST) {
       phys[m] = pos < np ? pos : 0;
+      const int pc = pos < n ? pos : n - 1;
 #pragma unroll
-      for (int c = 0; c < LU_NB; ++c)
-        P[m][c] = pos < n && c < n ? Ain[(size_t)pos * n + c] : (pos == c ? 1.0 : 0.0);
+      for (int c = 0; c < LU_NB; ++c) {
+        const double a = Ain[(size_t)pc * n + (c < n ? c : n - 1)];
+        P[m][c] = pos < n && c < n ? a : (pos == c ? 1.0 : 0.0);
+      }
     } else {
-      phys[m] = pos < np ? rmap[pos] : 0;
+      const int ph = rmap[pos < np ? pos : np - 1];
+      phys[m] = pos < np ? ph : 0;
 #pragma unroll
-      for (int c = 0; c < LU_NB; ++c) P[m][c] = pos < np ? M[(size_t)phys[m] * ld + k0 + c] : 0.0;
+      for (int c = 0; c < LU_NB; ++c) {
+        const double a = M[(size_t)ph * ld + k0 + c];
+        P[m][c] = pos < np ? a : 0.0;
+      }
     }
   }
 #pragma unroll
@@ -1384,23 +1393,25 @@ __device__ __forceinline__ void lu_factor_next(double* M, int ld, int np, const 
   lu_factor_panel<MR, false, 1>(M, ld, np, rmap, k0, lane, sh, lpos, phys, sg);
 }
 
-// U12 = L11^{-1} A12 for the columns [jc, jc + ncols) (ncols <= 16): lanes
-// 0 .. ncols-1 of the calling wave, one column each, column-oriented (step cc
-// subtracts L11[:, cc] u[cc] from the rows below: a dependency chain of 15).
-__device__ __forceinline__ void lu_u12_block(double* M, int ld, int k0, const int (&pr)[LU_NB], int jc, int ncols,
-                                             int lane) {
-  if (lane >= ncols) return;
-  const int j = jc + lane;
-  double u[LU_NB];
+// U12 of the right-hand-side column (column col): the panel's row c in lanes
+// c, c + 16, ... (lanes of equal c compute the same values; lanes 1 .. 15
+// store).  Step cc reads u[cc] across lanes and the rows below it subtract
+// L11[c][cc] u[cc]: the same FMAs in the same order as a column-oriented
+// forward substitution, branch-free (rows not below cc keep their value).
+__device__ __forceinline__ void lu_u12_rhs(double* M, int ld, int k0, const int* rmap, int col, int lane) {
+  const int c = lane & 15;
+  const int prow = rmap[k0 + c];
+  double u = M[(size_t)prow * ld + col];
+  double L[LU_NB - 1];
 #pragma unroll
-  for (int c = 0; c < LU_NB; ++c) u[c] = M[(size_t)pr[c] * ld + j];
+  for (int cc = 0; cc < LU_NB - 1; ++cc) L[cc] = M[(size_t)prow * ld + k0 + cc];
 #pragma unroll
   for (int cc = 0; cc < LU_NB - 1; ++cc) {
-#pragma unroll
-    for (int c = cc + 1; c < LU_NB; ++c) u[c] = fma(-M[(size_t)pr[c] * ld + k0 + cc], u[cc], u[c]);
+    const double x = readlane_d(u, cc);
+    const double upd = fma(-L[cc], x, u);
+    u = c > cc ? upd : u;
   }
-#pragma unroll
-  for (int c = 1; c < LU_NB; ++c) M[(size_t)pr[c] * ld + j] = u[c];
+  if (lane >= 1 && lane < LU_NB) M[(size_t)prow * ld + col] = u;
 }
 
 // The same for a full 16-column block with the whole wave: quad q (lanes
@@ -1427,12 +1438,18 @@ __device__ __forceinline__ void lu_u12_block16(double* M, int ld, int k0, const 
     prow[k] = rmap[k0 + g + 4 * k];
     u[k] = M[(size_t)prow[k] * ld + j];
   }
+  // branch-free: a lane whose row is not below cc computes the update and
+  // keeps its value (every address is in bounds), so no load waits inside a
+  // divergent branch on the chain
 #pragma unroll
   for (int cc = 0; cc < LU_NB - 1; ++cc) {
     const double x = quad_bcast(u[cc >> 2], cc & 3);
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (g + 4 * k > cc) u[k] = fma(-M[(size_t)prow[k] * ld + k0 + cc], x, u[k]);
+    for (int k = 0; k < 4; ++k) {
+      if (4 * k + 3 <= cc) continue;  // rows 4k .. 4k+3 all final
+      const double upd = fma(-M[(size_t)prow[k] * ld + k0 + cc], x, u[k]);
+      u[k] = 4 * k > cc || g + 4 * k > cc ? upd : u[k];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k)
@@ -1452,33 +1469,36 @@ __device__ __forceinline__ void lu_trail_rows(double* M, int ld, const int* rmap
   double bv[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) bv[s] = M[(size_t)brow[s] * ld + jc + li];
+  // A lone last tile row (ti + 1 == nt) runs the pair with its own rows in
+  // the second slot and does not store that slot: no load sits in a branch.
   for (int ti = t0; ti < nt; ti += tstep) {
     const bool two = ti + 1 < nt;
-    const int i0 = j0 + 16 * ti, i1 = i0 + 16;
-    const int arow0 = rmap[i0 + li], arow1 = two ? rmap[i1 + li] : arow0;
+    const int i0 = j0 + 16 * ti, i1 = two ? i0 + 16 : i0;
+    const int arow0 = rmap[i0 + li], arow1 = rmap[i1 + li];
     int crow0[4], crow1[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       crow0[r] = rmap[i0 + lk + 4 * r];
-      crow1[r] = two ? rmap[i1 + lk + 4 * r] : crow0[r];
+      crow1[r] = rmap[i1 + lk + 4 * r];
     }
     d4 acc0, acc1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       acc0[r] = M[(size_t)crow0[r] * ld + jc + li];
-      acc1[r] = two ? M[(size_t)crow1[r] * ld + jc + li] : 0.0;
+      acc1[r] = M[(size_t)crow1[r] * ld + jc + li];
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const double a0 = -M[(size_t)arow0 * ld + k0 + 4 * s + lk];
-      const double a1 = two ? -M[(size_t)arow1 * ld + k0 + 4 * s + lk] : 0.0;
+      const double a1 = -M[(size_t)arow1 * ld + k0 + 4 * s + lk];
       acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[s], acc0, 0, 0, 0);
       acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[s], acc1, 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      M[(size_t)crow0[r] * ld + jc + li] = acc0[r];
-      if (two) M[(size_t)crow1[r] * ld + jc + li] = acc1[r];
+    for (int r = 0; r < 4; ++r) M[(size_t)crow0[r] * ld + jc + li] = acc0[r];
+    if (two) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) M[(size_t)crow1[r] * ld + jc + li] = acc1[r];
     }
   }
 }
@@ -1508,7 +1528,9 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
                                         double* __restrict__ cout = nullptr,
                                         const double* __restrict__ rowmax = nullptr) {
   typedef double d4 __attribute__((ext_vector_type(4)));
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // the wave index through readfirstlane: the compiler then knows it (and
+  // every branch and loop bound taken from it) to be uniform across the wave
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int np = (n + LU_NB - 1) / LU_NB * LU_NB;
   const int ld = np + 1;  // odd: column accesses spread over the banks
   const int ncol = np + 1;
@@ -1543,26 +1565,31 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
   } else {
     // MR column chunks of 64 right of the panel cover np - 16 < 64 MR columns;
     // RB rows per batch keep 64 values in flight per lane
+    // (row r0 + 3 rr is uniform; every load reads a clamped, in-bounds
+    // address and a select drops what lies outside the matrix, so that the
+    // loads of a batch issue back to back)
     constexpr int CU = MR, RB = 64 / MR;
-    const int ncu = (np - LU_NB + 63) / 64;
     for (int r0 = wave - 1; r0 < np; r0 += 3 * RB) {
       double v_[RB][CU];
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) {
+        const int r = r0 + 3 * rr;
+        const double* __restrict__ Ar = Ain + (size_t)(r < n ? r : n - 1) * n;
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
-          const int r = r0 + 3 * rr, c = LU_NB + lane + 64 * u;
-          double val = (r == c) ? 1.0 : 0.0;
-          if (u < ncu && r < n && c < n) val = Ain[(size_t)r * n + c];
-          v_[rr][u] = val;
+          const int c = LU_NB + lane + 64 * u;
+          const double a = Ar[c < n ? c : n - 1];
+          v_[rr][u] = r < n && c < n ? a : (r == c ? 1.0 : 0.0);
         }
       }
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) {
+        const int r = r0 + 3 * rr;
+        if (r >= np) break;
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
-          const int r = r0 + 3 * rr, c = LU_NB + lane + 64 * u;
-          if (u < ncu && r < np && c < np) M[(size_t)r * ld + c] = v_[rr][u];
+          const int c = LU_NB + lane + 64 * u;
+          if (c < np) M[(size_t)r * ld + c] = v_[rr][u];
         }
       }
     }
@@ -1575,7 +1602,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
 #pragma unroll
     for (int c = 0; c < LU_NB; ++c) pr[c] = rmap[k0 + c];
     if (j0 >= np) {  // after the last panel only U12 of the right-hand side is left
-      if (wave == 0) lu_u12_block(M, ld, k0, pr, np, 1, lane);
+      if (wave == 0) lu_u12_rhs(M, ld, k0, rmap, np, lane);
       __syncthreads();
       break;
     }
@@ -1590,7 +1617,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
       lu_u12_block16(M, ld, k0, rmap, j0, lane);
     } else if (wave <= nblk) {
       if (wave < nblk) lu_u12_block16(M, ld, k0, rmap, j0 + 16 * wave, lane);
-      else lu_u12_block(M, ld, k0, pr, np, 1, lane);
+      else lu_u12_rhs(M, ld, k0, rmap, np, lane);
     }
     __syncthreads();
     // block 0's tile column by all four waves (tile rows dealt in pairs)
@@ -1612,7 +1639,7 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
           lu_trail_rows(M, ld, rmap, k0, j0, nblk, j0 + 16 * bk, brow, lane, 0, 2);
         } else {
           if (bk > 3) {
-            lu_u12_block(M, ld, k0, pr, np, 1, lane);
+            lu_u12_rhs(M, ld, k0, rmap, np, lane);
             wave_memory_sync();
           }
           lu_trail_rhs(M, ld, rmap, k0, j0, np, pr, lane);
@@ -1660,21 +1687,40 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
     // lanes (register row mi, lanes lb ..) work on one value wb: step cc reads
     // x = wb[lb + cc] / U[cc][cc] across lanes and subtracts U[:, cc] x from
     // every lane (lanes already solved keep their x in xv); then the rows
-    // above subtract the block's columns times x.
-    for (int i1 = np; i1 > 0; i1 -= LU_NB) {
-      const int i0 = i1 - LU_NB;
-      const int mi = i0 >> 6, lb = i0 & 63;
-      double wb = w[0];
+    // above subtract the block's columns times x.  Software-pipelined: a
+    // block's U columns for the rows above are requested before its chain and
+    // the next block's diagonal rows and reciprocal pivots during it; every
+    // register row is updated branch-free (prow is a valid row for every lane,
+    // rows at or below the block keep their value), so no load waits in a
+    // branch.
+    double ub[LU_NB], dv[LU_NB];
+    auto load_diag = [&](int i0) {
+      const int mi = i0 >> 6;
       int pb = prow[0];
 #pragma unroll
       for (int m = 1; m < MR; ++m)
-        if (mi == m) { wb = w[m]; pb = prow[m]; }
-      double ub[LU_NB], dv[LU_NB], xb[LU_NB];
+        if (mi == m) pb = prow[m];
 #pragma unroll
       for (int cc = 0; cc < LU_NB; ++cc) {
         ub[cc] = M[(size_t)pb * ld + i0 + cc];
         dv[cc] = sh.dinv[i0 + cc];
       }
+    };
+    load_diag(np - LU_NB);
+    for (int i1 = np; i1 > 0; i1 -= LU_NB) {
+      const int i0 = i1 - LU_NB;
+      const int mi = i0 >> 6, lb = i0 & 63;
+      double ur[MR][LU_NB];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+#pragma unroll
+        for (int cc = 0; cc < LU_NB; ++cc) ur[m][cc] = M[(size_t)prow[m] * ld + i0 + cc];
+      }
+      double wb = w[0];
+#pragma unroll
+      for (int m = 1; m < MR; ++m)
+        if (mi == m) wb = w[m];
+      double xb[LU_NB];
       double xv = 0.0;
 #pragma unroll
       for (int cc = LU_NB - 1; cc >= 0; --cc) {
@@ -1682,18 +1728,14 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
         xv = lane == lb + cc ? xb[cc] : xv;
         wb = fma(-ub[cc], xb[cc], wb);
       }
+      load_diag(i0 > 0 ? i0 - LU_NB : 0);
 #pragma unroll
       for (int m = 0; m < MR; ++m) {
         const int r = lane + 64 * m;
-        if (r < i0) {
-          const double* Ur = M + (size_t)prow[m] * ld + i0;
-          double s_ = w[m];
+        double s_ = w[m];
 #pragma unroll
-          for (int cc = 0; cc < LU_NB; ++cc) s_ = fma(-Ur[cc], xb[cc], s_);
-          w[m] = s_;
-        } else if (r < i1) {
-          w[m] = xv;
-        }
+        for (int cc = 0; cc < LU_NB; ++cc) s_ = fma(-ur[m][cc], xb[cc], s_);
+        w[m] = r < i0 ? s_ : (r < i1 ? xv : w[m]);
       }
     }
   } else {
