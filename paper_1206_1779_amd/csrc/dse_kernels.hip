@@ -1196,24 +1196,37 @@ template <int MR, int O>
 __device__ __forceinline__ LUPivot lu_pivot(const double (&P)[MR][LU_NB], const int (&lpos)[MR], int kc,
                                             int& sing) {
   double cand[MR];
-  double lmax = -1.0;
-  int lm = 0;
+  double lmax = -1.0, pl = P[0][O];
+  int lm = 0, ll = lpos[0];
+  if constexpr (MR <= 2) {
 #pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    cand[m] = lpos[m] >= kc ? fabs(P[m][O]) : -1.0;  // rows not yet used as pivots
-    if (cand[m] > lmax) {
-      lmax = cand[m];
-      lm = m;
+    for (int m = 0; m < MR; ++m) {
+      cand[m] = lpos[m] >= kc ? fabs(P[m][O]) : -1.0;  // rows not yet used as pivots
+      if (cand[m] > lmax) {
+        lmax = cand[m];
+        lm = m;
+      }
+    }
+#pragma unroll
+    for (int m = 1; m < MR; ++m)
+      if (lm == m) {
+        pl = P[m][O];
+        ll = lpos[m];
+      }
+  } else {
+    // more register rows: the row's value and position are picked up in the
+    // same scan (an index into P taken after it makes the compiler move P to
+    // scratch memory)
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      cand[m] = lpos[m] >= kc ? fabs(P[m][O]) : -1.0;
+      const bool gt = cand[m] > lmax;
+      lmax = gt ? cand[m] : lmax;
+      lm = gt ? m : lm;
+      pl = gt ? P[m][O] : pl;
+      ll = gt ? lpos[m] : ll;
     }
   }
-  double pl = P[0][O];
-  int ll = lpos[0];
-#pragma unroll
-  for (int m = 1; m < MR; ++m)
-    if (lm == m) {
-      pl = P[m][O];
-      ll = lpos[m];
-    }
   const double il = recip_any(pl);
   const unsigned key = lmax >= 0.0 ? (unsigned)((unsigned long long)__double_as_longlong(lmax) >> 32) : 0u;
   const unsigned kmax = wave_max_u32(key);
@@ -1585,11 +1598,10 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) {
         const int r = r0 + 3 * rr;
-        if (r >= np) break;
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
           const int c = LU_NB + lane + 64 * u;
-          if (c < np) M[(size_t)r * ld + c] = v_[rr][u];
+          if (r < np && c < np) M[(size_t)r * ld + c] = v_[rr][u];
         }
       }
     }
