@@ -31,11 +31,23 @@ namespace {
 // step old) and one FMA P_{k+1} = v P_k - q on it; no division in the loop.
 //
 // One lane per positive root (roots come in pairs +-x): root k counted from
-// +1, started at Tricomi's estimate (1 - (n-1)/(8 n^3)) cos(pi (4k-1)/(4n+2)).
-// Newton steps x <- x - P_n/P_n' until the step is below 1e-16, then one more
-// recurrence at the final node for P_n' and the weight
-// w = 2 / ((1 - x^2) P_n'^2), P_n' = n (x P_n - P_{n-1}) / (x^2 - 1).  A
-// wave keeps iterating while any of its lanes has not finished.
+// +1.  Start: the five roots nearest +1 at theta = j_{0,k} / (n + 1/2), the
+// zeros of J_0 scaled as the Mehler-Heine limit P_n(cos(z / n)) -> J_0(z)
+// puts them (exact to double precision for large n, where Tricomi's estimate
+// is off by up to 5e-13 at k = 1 and the edge roots would need two more
+// Newton steps); the others at Tricomi's estimate
+// (1 - (n-1)/(8 n^3)) cos(pi (4k-1)/(4n+2)).
+// Newton steps x <- x - h, h = P_n/P_n', P_n' = n (x P_n - P_{n-1}) / (x^2 - 1),
+// until the step taken is small enough to finish on it: at a root
+// P_n''/P_n' = 2x/(1 - x^2) and P_n'''/P_n' = O(n^2/(1 - x^2)) (Legendre's
+// equation), so the node after the step is off by about |x| h^2/(1 - x^2)
+// and the first-order value P_n' - h P_n'' at the new node by a relative
+// n^2 h^2; both must stay below the rounding level (|x| h^2 <= u (1 - x^2)/4
+// and n^2 h^2 <= u, u = 2^-53).  The weight w = 2 / ((1 - x^2) P_n'^2) then
+// takes that first-order derivative (P_n'' from Legendre's equation, h the
+// step as rounded), so the last recurrence is also the last Newton step: at
+// n = 2^17 every root is final after one recurrence.  A wave keeps
+// iterating while any of its lanes has not finished.
 
 
 // beta[k-1] = k/(k+1) for k = 1 .. n-1, then 2 kGLGroup zeros (the read-ahead
@@ -98,23 +110,29 @@ __global__ __launch_bounds__(256) void gl_node_kernel(int n, const double* __res
   const int k = blockIdx.x * 256 + threadIdx.x + 1;
   const bool act = k <= nh;
   const double dn = (double)n;
+  // the first zeros of J_0 (Abramowitz and Stegun, Table 9.5)
+  constexpr double kJ0[5] = {2.404825557695773, 5.520078110286311, 8.653727912911013, 11.79153443901428,
+                             14.93091770848779};
+  constexpr double kU = 1.1102230246251565e-16;  // 2^-53
   double s = 0.5;  // inactive lanes run along on a harmless point
-  if (act) s = (1.0 - (dn - 1.0) / (8.0 * dn * dn * dn)) * cos(kPi * (4.0 * k - 1.0) / (4.0 * dn + 2.0));
-  bool done = !act, last = false;
+  if (act)
+    s = k <= 5 ? cos(kJ0[k - 1] / (dn + 0.5))
+               : (1.0 - (dn - 1.0) / (8.0 * dn * dn * dn)) * cos(kPi * (4.0 * k - 1.0) / (4.0 * dn + 2.0));
+  bool done = !act;
   double dp = 1.0;
   for (int it = 0; it < 100 && __any(done ? 0 : 1); ++it) {
     double pn, pn1;
     legendre_wave(n, s, beta, pn, pn1);
-    const double d = dn * (s * pn - pn1) / (s * s - 1.0);
     if (!done) {
-      if (last) {
-        dp = d;
+      const double d = dn * (s * pn - pn1) / (s * s - 1.0);
+      const double sn = s - pn / d;
+      const double h = s - sn;  // the step as taken (exact)
+      const double om = 1.0 - s * s;
+      if (fabs(s) * h * h <= 0.25 * kU * om && dn * dn * h * h <= kU) {
+        dp = d - h * (2.0 * s * d - dn * (dn + 1.0) * pn) / om;  // P_n' at sn, to first order
         done = true;
-      } else {
-        const double ds = pn / d;
-        s -= ds;
-        if (fabs(ds) < 1e-16) last = true;
       }
+      s = sn;
     }
   }
   if (act) {
