@@ -731,6 +731,17 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by, in
     }
     return;
   }
+  // this thread's output element (ri, cj) of the tile, and for gluon rows
+  // the k-side partial sums of the same target, requested before the product
+  // so that their loads overlap the operand loads
+  const int ri = t >> 4, cj = t & 15;
+  const int orow = r0 + ri, ocol = j0 + cj;
+  acc_t ds_ = 0;
+  if (orow < 2 * v.RZ) {  // groups a, b are contiguous
+    const acc_t* src = Dp + (size_t)orow * dstride + ocol;
+#pragma unroll 4
+    for (int k = tlo; k < thi; ++k) ds_ += src[(size_t)k * NJ];
+  }
   const int qper = Qp / kCS / 4;
   const int qbeg = part * (Qp / kCS) + wave * qper;
   const int i = lane & 15, kk = lane >> 4;
@@ -766,22 +777,14 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by, in
   }
   __syncthreads();
   {
-    // one output element per thread: (ri, cj) of the tile.  Result layouts:
+    // one output element per thread.  Result layouts:
     // v_mfma_f64_16x16x4f64, lane l, register r: D[l/16 + 4 r][l % 16];
     // v_mfma_f32_16x16x4f32, lane l, register r: D[4 (l/16) + r][l % 16]
-    const int ri = t >> 4, cj = t & 15;
     const int l = MIX ? (ri >> 2) * 16 + cj : (ri & 3) * 16 + cj;
     const int rg = MIX ? (ri & 3) : (ri >> 2);
     acc_t sum = ((part_[0][rg][l] + part_[1][rg][l]) + part_[2][rg][l]) + part_[3][rg][l];
-    const int row = r0 + ri, col = j0 + cj;
-    if (row < 2 * v.RZ) {  // gluon rows: add the k-side sums of the same target
-      const acc_t* src = Dp + (size_t)row * dstride + col;  // groups a, b are contiguous
-      acc_t ds_ = 0;
-#pragma unroll 4
-      for (int k = tlo; k < thi; ++k) ds_ += src[(size_t)k * NJ];
-      sum += ds_;
-    }
-    reinterpret_cast<acc_t*>(v.Eq)[((size_t)part * v.Rbp + row) * NJ + col] = sum;
+    if (orow < 2 * v.RZ) sum += ds_;  // gluon rows: the k-side sums of the same target
+    reinterpret_cast<acc_t*>(v.Eq)[((size_t)part * v.Rbp + orow) * NJ + ocol] = sum;
   }
 }
 
@@ -856,6 +859,9 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
   const size_t es = (size_t)v.Rbp * v.NJ, gs = (size_t)v.RG * v.NJ;  // part strides
   const int t = threadIdx.x;
   const int NJ = v.NJ, n = v.n;
+  // the row's residual by the last wave, before its matrix entries (for
+  // n <= 192 it has none): its loads then overlap those of the entries
+  if (F && t >= 192) row_residual_wave(v, ph, r, F, S, t - 192, F2, S2);
   const bool gl = r < v.n_z;
   const int i = gl ? r : r - v.n_z;
   const double d = exp(-v.lnX[r]);
@@ -900,7 +906,6 @@ __device__ __forceinline__ void assemble_body(const Views& v, const Phys& ph, in
     __syncthreads();
     if (t == 0) v.rowmax[r] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   }
-  if (F && t < 64) row_residual_wave(v, ph, r, F, S, t, F2, S2);
 }
 
 template <bool MIX>
