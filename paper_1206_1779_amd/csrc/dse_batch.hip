@@ -177,13 +177,15 @@ dse_status eval_residuals(dse_batch* B, const double* cpk, int which) {
   return DSE_OK;
 }
 
-dse_status eval_jacobians(dse_batch* B, const double* cpk) {
+// which 1: at each member's trial point ct (cpk unused)
+dse_status eval_jacobians(dse_batch* B, const double* cpk, int which = 0) {
   const dse::BatchArgs& a = B->args;
   if (B->fused) {
-    BHIP_TRY(B, dse::launch_batch_fused(a, cpk, B->d_items, B->n_items, B->tpi, B->grid, B->d_counter, B->st));
+    BHIP_TRY(B, dse::launch_batch_fused(a, cpk, B->d_items, B->n_items, B->tpi, B->grid, B->d_counter, B->st,
+                                        which));
     return DSE_OK;
   }
-  BHIP_TRY(B, dse::launch_batch_dressing(a, cpk, 0, B->d_counter, B->st));
+  BHIP_TRY(B, dse::launch_batch_dressing(a, cpk, which, B->d_counter, B->st));
   BHIP_TRY(B, dse::launch_batch_points(a, B->d_items, B->n_items, 1, B->grid, B->tpi, B->d_counter, B->st));
   BHIP_TRY(B, dse::launch_batch_contract(a, B->st));
   BHIP_TRY(B, dse::launch_batch_assemble(a, B->st));
@@ -499,19 +501,22 @@ dse_status dse_batch_newton_solve(dse_batch* B, double* d_c, const dse_newton_op
   std::vector<double> f(N), f2(N), nrm;
   std::vector<int> extra(N, 0), done(N, 0), conv(N, 0), searching(N, 0), accepted(N, 0);
   std::vector<dse_status> status(N, DSE_OK);
-  // residual at the start points
+  // J, F, S at the start points: as in the single-problem solve, every
+  // evaluation of an accepted point is an assembly, so the next iteration's
+  // matrix comes with the residual that accepts it
   std::fill(B->h_mask.begin(), B->h_mask.end(), 1);
   std::fill(B->h_rho.begin(), B->h_rho.end(), 1.0);
   dse_status s = upload_ctl(B);
-  if (s == DSE_OK) s = eval_residuals(B, d_c, 0);
+  if (s == DSE_OK) s = eval_jacobians(B, d_c);
   if (s == DSE_OK) s = read_nrm(B, 0, nrm);
   if (s != DSE_OK) return s;
+  std::vector<int> have_J(N, 1);  // the workspace's J belongs to the member's current point
   for (int b = 0; b < N; ++b) {
     f[b] = nrm[4 * b];
     f2[b] = nrm[4 * b + 3];
     R[b].fnorm_hist[0] = f[b];
     R[b].fnorm2 = nrm[4 * b + 1];
-    R[b].n_residuals = 1;
+    R[b].n_jacobians = 1;
     if (!isfinite(f[b])) { status[b] = DSE_E_NONFINITE; done[b] = 1; }
   }
   std::vector<double> ft(N, INFINITY), ft2(N, INFINITY), dinf(N, 0.0), fn2t(N, 0.0);
@@ -533,25 +538,47 @@ dse_status dse_batch_newton_solve(dse_batch* B, double* d_c, const dse_newton_op
       ++nact;
     }
     if (nact == 0) break;
+    // the matrix at the current point, for the members whose last step was
+    // relaxed (their workspace holds a trial's matrix)
+    std::vector<int> act(B->h_mask);
+    int nre = 0;
+    for (int b = 0; b < N; ++b) {
+      B->h_mask[b] = act[b] && !have_J[b];
+      if (B->h_mask[b]) { ++nre; ++R[b].n_jacobians; }
+    }
+    if (nre > 0) {
+      if ((s = upload_ctl(B)) != DSE_OK) return s;
+      if ((s = eval_jacobians(B, d_c)) != DSE_OK) return s;
+    }
+    B->h_mask = act;
     if ((s = upload_ctl(B)) != DSE_OK) return s;
-    if ((s = eval_jacobians(B, d_c)) != DSE_OK) return s;
     BHIP_TRY(B, dse::launch_batch_lu(B->args, B->d_flags, B->st));
     for (int b = 0; b < N; ++b) {
       searching[b] = B->h_mask[b];
       accepted[b] = 0;
-      if (searching[b]) ++R[b].n_jacobians;
     }
     for (int h = 0;; ++h) {
       BHIP_TRY(B, dse::launch_batch_axpy(B->args, d_c, B->d_rho, B->st));
-      if ((s = eval_residuals(B, nullptr, 1)) != DSE_OK) return s;
-      if ((s = read_nrm(B, 1, nrm)) != DSE_OK) return s;
       if (h == 0) {
+        // the full step in Jacobian mode: accepted, its matrix is the next one
+        if ((s = eval_jacobians(B, nullptr, 1)) != DSE_OK) return s;
+        if ((s = read_nrm(B, 2, nrm)) != DSE_OK) return s;
         BHIP_TRY(B, hipMemcpy(flags.data(), B->d_flags, N * sizeof(int), hipMemcpyDeviceToHost));
+      } else {
+        // relaxed steps in residual mode
+        if ((s = eval_residuals(B, nullptr, 1)) != DSE_OK) return s;
+        if ((s = read_nrm(B, 1, nrm)) != DSE_OK) return s;
       }
       int still = 0;
       for (int b = 0; b < N; ++b) {
         if (!searching[b]) continue;
-        ++R[b].n_residuals;
+        if (h == 0) {
+          ++R[b].n_jacobians;
+          have_J[b] = 1;
+        } else {
+          ++R[b].n_residuals;
+          have_J[b] = 0;
+        }
         if (h == 0 && flags[b] == DSE_E_SINGULAR) {
           status[b] = DSE_E_SINGULAR;
           done[b] = 1;
@@ -574,12 +601,13 @@ dse_status dse_batch_newton_solve(dse_batch* B, double* d_c, const dse_newton_op
       for (int b = 0; b < N; ++b) B->h_mask[b] = searching[b];
       if ((s = upload_ctl(B)) != DSE_OK) return s;
     }
-    // take the accepted steps
+    // take the accepted steps (mask 2: the full step, whose F and S the
+    // Jacobian-mode assembly wrote in place; 1: a relaxed one)
     for (int b = 0; b < N; ++b) {
       B->h_mask[b] = 0;
       if (!accepted[b]) continue;
       if (!isfinite(ft[b])) { status[b] = DSE_E_NONFINITE; done[b] = 1; continue; }
-      B->h_mask[b] = 1;
+      B->h_mask[b] = have_J[b] ? 2 : 1;
     }
     if ((s = upload_ctl(B)) != DSE_OK) return s;
     BHIP_TRY(B, dse::launch_batch_accept(B->args, d_c, B->st));

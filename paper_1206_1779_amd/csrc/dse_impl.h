@@ -187,8 +187,9 @@ int batch_points_occupancy(int mode, int max_nj);  // resident blocks per CU
 // The whole Newton-matrix assembly (dressings, points, contraction, rows) in
 // one cooperative launch of grid resident blocks (at most the occupancy of
 // batch_fused_occupancy times the CUs).
+// which 1: the dressings at each member's trial point ct instead of cpk.
 hipError_t launch_batch_fused(const BatchArgs& a, const double* cpk, const int4* items, int n_items, int tpi,
-                              int grid, int* counter, hipStream_t st);
+                              int grid, int* counter, hipStream_t st, int which = 0);
 int batch_fused_occupancy(int max_nj);  // resident blocks per CU (0: not available)
 hipError_t launch_batch_contract(const BatchArgs& a, hipStream_t st);
 hipError_t launch_batch_assemble(const BatchArgs& a, hipStream_t st);

@@ -2024,7 +2024,7 @@ __global__ __launch_bounds__(256) void batch_assemble_kernel(const SolveDesc* __
 template <int NJMAX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_fused_kernel(
     BatchArgs a, const double* __restrict__ cpk, const int4* __restrict__ items, int n_items, int tpi,
-    int* counter) {
+    int* counter, int which) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
   __shared__ double smem[point_smem<NJMAX, true>()];
@@ -2037,7 +2037,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     const int b = u / a.max_dress_blocks, blk = u - b * a.max_dress_blocks;
     if (a.mask[b]) {
       const SolveDesc& sd = d[b];
-      dressing_body(sd.v, sd.ph, cpk + sd.coff, blk * 256, a.max_dress_blocks * 256, blk == 0);
+      dressing_body(sd.v, sd.ph, which ? sd.v.ct : cpk + sd.coff, blk * 256, a.max_dress_blocks * 256, blk == 0);
     }
     __syncthreads();
   }
@@ -2089,13 +2089,15 @@ __global__ __launch_bounds__(256) void batch_residual_rows_kernel(const SolveDes
     row_residual_wave(sd.v, sd.ph, r, which ? sd.v.Ft : sd.v.F, which ? sd.v.St : sd.v.S, threadIdx.x & 63);
 }
 
+// which: 0 F and S; 1 the trial's Ft and St with ||delta||_inf; 2 F and S
+// with ||delta||_inf (a trial point assembled in Jacobian mode)
 __global__ __launch_bounds__(256) void batch_norms_kernel(const SolveDesc* __restrict__ d,
                                                           const int* __restrict__ mask, int which,
                                                           double* out) {
   const int b = blockIdx.x;
   if (!mask[b]) return;
   const Views& v = d[b].v;
-  norms_body(v.n, which ? v.Ft : v.F, which ? v.St : v.S, which ? v.dlt : nullptr, out + 4 * b);
+  norms_body(v.n, which == 1 ? v.Ft : v.F, which == 1 ? v.St : v.S, which ? v.dlt : nullptr, out + 4 * b);
 }
 
 // One workgroup per system: J delta = F.
@@ -2121,6 +2123,8 @@ __global__ __launch_bounds__(256) void batch_axpy_kernel(const SolveDesc* __rest
   if (i < sd.v.n) sd.v.ct[i] = cpk[sd.coff + i] - rho[b] * sd.v.dlt[i];
 }
 
+// mask 1: the trial was evaluated in residual mode (Ft, St become F, S);
+// mask 2: in Jacobian mode (F and S hold it already)
 __global__ __launch_bounds__(256) void batch_accept_kernel(const SolveDesc* __restrict__ d,
                                                            const int* __restrict__ mask, double* cpk) {
   const int b = blockIdx.y;
@@ -2129,8 +2133,10 @@ __global__ __launch_bounds__(256) void batch_accept_kernel(const SolveDesc* __re
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < sd.v.n) {
     cpk[sd.coff + i] = sd.v.ct[i];
-    sd.v.F[i] = sd.v.Ft[i];
-    sd.v.S[i] = sd.v.St[i];
+    if (mask[b] == 1) {
+      sd.v.F[i] = sd.v.Ft[i];
+      sd.v.S[i] = sd.v.St[i];
+    }
   }
 }
 
@@ -2407,11 +2413,11 @@ int batch_fused_occupancy(int max_nj) {
 }
 
 hipError_t launch_batch_fused(const BatchArgs& a, const double* cpk, const int4* items, int n_items, int tpi,
-                              int grid, int* counter, hipStream_t st) {
+                              int grid, int* counter, hipStream_t st, int which) {
   const void* f = fused_kernel_for(a.max_nj);
   if (!f || grid < 1 || tpi < 1) return hipErrorInvalidValue;
   BatchArgs aa = a;
-  void* args[] = {&aa, (void*)&cpk, (void*)&items, &n_items, &tpi, &counter};
+  void* args[] = {&aa, (void*)&cpk, (void*)&items, &n_items, &tpi, &counter, &which};
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(256), args, 0, st);
 }
 
