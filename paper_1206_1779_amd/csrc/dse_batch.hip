@@ -53,6 +53,14 @@ struct dse_batch {
   dse::BatchArgs args{};
   std::vector<int> h_mask;
   std::vector<double> h_rho;
+  // pinned host words for the device-to-host reads the host waits on (norms
+  // [count][4], then the pivot flags [count] as int): a copy to pageable
+  // memory would wait for the stream by itself
+  double* h_pin = nullptr;
+  int* h_pin_flags() { return reinterpret_cast<int*>(h_pin + 4 * (size_t)count); }
+  ~dse_batch() {
+    if (h_pin) (void)hipHostFree(h_pin);
+  }
   std::vector<int64_t> coff, joff;
   char err[512] = {0};
 };
@@ -198,11 +206,19 @@ int fused_grid(const dse_batch* B) {
   return dse::batch_fused_occupancy(B->args.max_nj) * B->ncu;
 }
 
-dse_status read_nrm(dse_batch* B, int which, std::vector<double>& out) {
+// with_flags: the pivot flags come back with the norms (one wait)
+dse_status read_nrm(dse_batch* B, int which, std::vector<double>& out, std::vector<int>* flags = nullptr) {
   BHIP_TRY(B, dse::launch_batch_norms(B->args, which, B->d_nrm, B->st));
   out.resize(4 * (size_t)B->count);
-  BHIP_TRY(B, hipMemcpyAsync(out.data(), B->d_nrm, out.size() * sizeof(double), hipMemcpyDeviceToHost, B->st));
+  BHIP_TRY(B, hipMemcpyAsync(B->h_pin, B->d_nrm, out.size() * sizeof(double), hipMemcpyDeviceToHost, B->st));
+  if (flags)
+    BHIP_TRY(B, hipMemcpyAsync(B->h_pin_flags(), B->d_flags, B->count * sizeof(int), hipMemcpyDeviceToHost, B->st));
   BHIP_TRY(B, hipStreamSynchronize(B->st));
+  memcpy(out.data(), B->h_pin, out.size() * sizeof(double));
+  if (flags) {
+    flags->resize(B->count);
+    memcpy(flags->data(), B->h_pin_flags(), B->count * sizeof(int));
+  }
   return DSE_OK;
 }
 
@@ -276,6 +292,13 @@ dse_status dse_batch_init(const dse_params* p, int32_t count, void* d_workspace,
   B->max_items = s.max_items;
   if (hipGetDevice(&B->device) != hipSuccess) {
     set_err(g_batch_err, "hipGetDevice failed");
+    delete B;
+    return DSE_E_DEVICE;
+  }
+  if (hipHostMalloc((void**)&B->h_pin, (size_t)count * (4 * sizeof(double) + sizeof(int)), hipHostMallocDefault) !=
+      hipSuccess) {
+    B->h_pin = nullptr;
+    set_err(g_batch_err, "hipHostMalloc failed");
     delete B;
     return DSE_E_DEVICE;
   }
@@ -562,8 +585,7 @@ dse_status dse_batch_newton_solve(dse_batch* B, double* d_c, const dse_newton_op
       if (h == 0) {
         // the full step in Jacobian mode: accepted, its matrix is the next one
         if ((s = eval_jacobians(B, nullptr, 1)) != DSE_OK) return s;
-        if ((s = read_nrm(B, 2, nrm)) != DSE_OK) return s;
-        BHIP_TRY(B, hipMemcpy(flags.data(), B->d_flags, N * sizeof(int), hipMemcpyDeviceToHost));
+        if ((s = read_nrm(B, 2, nrm, &flags)) != DSE_OK) return s;
       } else {
         // relaxed steps in residual mode
         if ((s = eval_residuals(B, nullptr, 1)) != DSE_OK) return s;

@@ -510,8 +510,9 @@ dse_status flush_timings(dse_ctx* ctx) {
 // Reads max_r |F_r|/S_r, ||F||_2, ||d||_inf and ||F/S||_2 (synchronises the stream).
 dse_status read_norms(dse_ctx* ctx, const double* F, const double* S, const double* d, double out[4]) {
   HIP_TRY(ctx, dse::launch_norms(ctx->v, F, S, d, ctx->v.scal, ctx->st));
-  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->v.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->hpin, ctx->v.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
+  for (int i = 0; i < 4; ++i) out[i] = ctx->hpin[i];
   return DSE_OK;
 }
 
@@ -598,12 +599,20 @@ dse_status dse_init(const dse_params* p, void* d_workspace, size_t ws_bytes, voi
         return DSE_E_DEVICE;
       }
     }
+  if (hipHostMalloc((void**)&ctx->hpin, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    set_err(g_init_err, "hipHostMalloc failed");
+    for (auto& row : ctx->ev)
+      for (auto& e : row) (void)hipEventDestroy(e);
+    delete ctx;
+    return DSE_E_DEVICE;
+  }
   dse::lu_setup();
   s = build_tables(ctx);
   if (s != DSE_OK) {
     set_err(g_init_err, "%s", ctx->err);
     for (auto& row : ctx->ev)
       for (auto& e : row) (void)hipEventDestroy(e);
+    (void)hipHostFree(ctx->hpin);
     delete ctx;
     return s;
   }
@@ -620,6 +629,7 @@ dse_status dse_destroy(dse_ctx* ctx) {
   for (auto& e : ctx->nev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
+  if (ctx->hpin) (void)hipHostFree(ctx->hpin);
   delete ctx;
   return DSE_OK;
 }
@@ -732,9 +742,9 @@ dse_status dse_lu_solve(dse_ctx* ctx, const double* d_J, const double* d_b, doub
   DeviceGuard dg(ctx->device);
   HIP_TRY(ctx, dse::launch_row_absmax(ctx->v.n, d_J, ctx->v.rowmax_u, ctx->st));
   HIP_TRY(ctx, dse::launch_lu_solve(ctx->v, d_J, d_b, d_x, trans, ctx->st, nullptr, 0.0, nullptr, ctx->v.rowmax_u));
-  int32_t flag = 0;
-  HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->hflag(), ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
+  const int32_t flag = *ctx->hflag();
   if (flag == DSE_E_SINGULAR) {
     set_err(ctx->err, "singular matrix: a pivot is zero, not finite, or below n eps times its row's largest entry");
     return DSE_E_SINGULAR;
@@ -873,10 +883,9 @@ dse_status dse_newton_step(dse_ctx* ctx, const double* d_c, double rho, double* 
   }
   ctx->jac_at = d_c_new;
   if (check) {
-    int32_t flag = 0;
-    HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->hflag(), ctx->v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->st));
-    if (flag == DSE_E_SINGULAR) {
+    if (*ctx->hflag() == DSE_E_SINGULAR) {
       ctx->jac_at = nullptr;
       set_err(ctx->err, "zero pivot");
       return DSE_E_SINGULAR;
@@ -970,7 +979,7 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
         have_J = true;
         j_mix = use_mix;
         // the pivot flag arrives with the norms (one synchronisation)
-        HIP_TRY(ctx, hipMemcpyAsync(&flag, v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->hflag(), v.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       } else {
         // relaxed steps in residual mode
         HIP_TRY(ctx, dse::launch_axpy(n, d_c, rho, v.dlt, v.ct, st));
@@ -979,6 +988,7 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
         have_J = false;
       }
       if ((s = read_norms(ctx, v.F, v.S, v.dlt, nrm)) != DSE_OK) { status = s; break; }
+      if (h == 0) flag = *ctx->hflag();  // copied before the norms, complete after their wait
       if (h == 0) {
         // read_norms synchronised the stream: the phase events are complete
         float ma = 0.f, ml = 0.f;

@@ -220,6 +220,10 @@ struct dse_ctx {
   hipEvent_t ev[kRing][kEv];
   // device time of the assembly and LU phases of dse_newton_solve
   hipEvent_t nev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // pinned host words for the small reads the host waits on (norms, pivot
+  // flag): a copy to pageable memory would wait for the stream by itself
+  double* hpin = nullptr;  // [0..3] norms, [4] flag (as int32)
+  int32_t* hflag() { return reinterpret_cast<int32_t*>(hpin + 4); }
   int ring_count;
   double acc_ms[5];
   int acc_n;
