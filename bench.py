@@ -71,6 +71,23 @@ def measured_traffic(kernel: str):
         return None
 
 
+# compiler flags of the oracle library the CPU timings use (set in main)
+ORACLE_BUILD = "gcc -O2 -fopenmp (portable build)"
+
+
+def select_oracle_build() -> None:
+    """Times the oracle as built for this host (-O3 -march=native, FMA
+    contraction off: the same arithmetic as the portable -O2 build the tests
+    use); keeps the portable build when that compile fails."""
+    global ORACLE_BUILD
+    import subprocess
+    import oracle
+    try:
+        ORACLE_BUILD = oracle.use_native_build()
+    except (RuntimeError, OSError, subprocess.CalledProcessError) as e:
+        print("oracle: host-tuned build unavailable (%s), timing the portable one" % e, file=sys.stderr)
+
+
 def cpu_baseline(cfg: dict, c, cpu_seconds: float = 20.0, max_steps: int = 50) -> dict:
     """The oracle (plain FP64 C, OpenMP over rows, all host threads) doing the
     same step on the host: LU solve of the held Newton matrix, update, Newton
@@ -93,7 +110,7 @@ def cpu_baseline(cfg: dict, c, cpu_seconds: float = 20.0, max_steps: int = 50) -
         if dt * threads >= cpu_seconds or steps >= max_steps:
             break
     return {"value": n * n * steps / dt, "unit": "Jacobian entries/s", "cores": threads,
-            "kind": "oracle", "seconds": dt, "steps": steps,
+            "kind": "oracle", "build": ORACLE_BUILD, "seconds": dt, "steps": steps,
             "sample": "%d Newton iterations (LU solve, update, J and F at the new point) of the N=64 "
                       "workload from the start guess, %d host threads" % (steps, threads)}
 
@@ -350,7 +367,7 @@ def bench_schwinger(dse, workloads, torch, with_cpu: bool = True) -> dict:
         oracle.schwinger(p, c.cpu().numpy(), tt, n=nc, p_max=W["p_max"])
         t_all = time.perf_counter() - tc0
         # the rule is O(n^2) (n recurrence steps per node), the sum O(n m)
-        out["cpu_oracle"] = {"nodes": nc, "times": len(tt), "threads": oracle.get_threads(),
+        out["cpu_oracle"] = {"nodes": nc, "times": len(tt), "threads": oracle.get_threads(), "build": ORACLE_BUILD,
                              "gl_s": t_gl, "total_s": t_all,
                              "total_s_extrapolated_to_nodes": t_gl * (n / nc) ** 2
                              + max(t_all - t_gl, 0.0) * (n / nc)}
@@ -466,6 +483,8 @@ def main() -> int:
     from paper_1206_1779_amd import dse
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not args.no_cpu and not args.copy_calibration:
+        select_oracle_build()
     if args.copy_calibration:
         nb = args.copy_calibration << 20
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")

@@ -22,20 +22,42 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dse_ref.c")
 _LIB = os.path.join(_HERE, "libdse_ref.so")
+_LIB_NATIVE = os.path.join(_HERE, "libdse_ref_native.so")
 
 
-def build(force: bool = True) -> str:
+_NATIVE_FLAGS = ["-O3", "-march=native", "-ffp-contract=off"]
+_native = False
+
+
+def build(force: bool = True, native: bool = False) -> str:
     """Compile the oracle into ``oracle/libdse_ref.so`` (gcc, -O2, OpenMP).
 
     No -ffast-math (it would undo the compensated sums) and no -march=native
-    (the library is built here and may run on another host)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-               "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+    (the library is built here and may run on another host).  native: a second
+    library, ``oracle/libdse_ref_native.so``, for the host it is built on
+    (-O3 -march=native, FMA contraction off so that the arithmetic stays that
+    of the -O2 build); the CPU baseline is timed with it."""
+    out = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp%d" % os.getpid()
+        flags = _NATIVE_FLAGS if native else ["-O2"]
+        cmd = ["gcc"] + flags + ["-std=c11", "-fPIC", "-shared", "-fopenmp",
+                                 "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
+
+
+def use_native_build() -> str:
+    """Build the host-tuned library and load it instead of the portable one
+    (before any other call of this module in the process); returns the
+    compiler flags in use."""
+    global _native
+    if _lib is not None:
+        raise RuntimeError("the oracle library is loaded already")
+    build(force=True, native=True)
+    _native = True
+    return " ".join(["gcc"] + _NATIVE_FLAGS + ["-fopenmp"])
 
 
 class Params(C.Structure):
@@ -67,9 +89,10 @@ _D = C.POINTER(C.c_double)
 def load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        lib = C.CDLL(_LIB)
+        path = _LIB_NATIVE if _native else _LIB
+        if not os.path.exists(path):
+            build(force=False, native=_native)
+        lib = C.CDLL(path)
         P = C.POINTER(Params)
         sig = {
             "dse_ref_gauss_legendre": (C.c_int, [C.c_int, _D, _D]),
