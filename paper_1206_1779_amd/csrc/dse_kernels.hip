@@ -1595,8 +1595,10 @@ __device__ __forceinline__ void lu_body(int n, const double* __restrict__ Ain, c
     // RB rows per batch keep 64 values in flight per lane
     // (row r0 + 3 rr is uniform; every load reads a clamped, in-bounds
     // address and a select drops what lies outside the matrix, so that the
-    // loads of a batch issue back to back)
-    constexpr int CU = MR, RB = 64 / MR;
+    // loads of a batch issue back to back).  Two register rows: 48 rows per
+    // wave and batch, so that the three waves cover n <= 128 in one batch,
+    // one memory round trip (96 values in flight per lane).
+    constexpr int CU = MR, RB = MR == 2 ? 48 : 64 / MR;
     for (int r0 = wave - 1; r0 < np; r0 += 3 * RB) {
       double v_[RB][CU];
 #pragma unroll
