@@ -752,8 +752,11 @@ __device__ __forceinline__ void contract_body(const Views& v, int bx, int by, in
 #pragma unroll 4
     for (int k = tlo; k < thi; ++k) ds_ += src[(size_t)k * NJ];
   }
-  const int qper = Qp / kCS / 4;
-  const int qbeg = part * (Qp / kCS) + wave * qper;
+  // this wave's MFMA steps (4 radial nodes each): the Qp / 4 steps split
+  // evenly over the kCS parts x 4 waves
+  const int nsteps = Qp / 4, wpart = part * 4 + wave;
+  const int sbeg = wpart * nsteps / (4 * kCS), send = (wpart + 1) * nsteps / (4 * kCS);
+  const int qbeg = 4 * sbeg, qper = 4 * (send - sbeg);
   const int i = lane & 15, kk = lane >> 4;
   const acc_t* A = reinterpret_cast<const acc_t*>(v.Bm) + (size_t)(r0 + i) * Qp + kk;
   const size_t kstride = (size_t)v.Rbp * Qp;  // angular slices of B
