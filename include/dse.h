@@ -268,7 +268,7 @@ dse_status dse_newton_solve(dse_ctx* ctx, double* d_c, const dse_newton_opts* op
  * launch sequence is recorded into a HIP graph on the first call for a given
  * set of pointers and rho and replayed afterwards (the arrays must stay
  * allocated while the context uses them).  Kernel by kernel is the default
- * because it measured faster on MI355X (0.142 against 0.147 ms per step at
+ * because it measured faster on MI355X (0.140 against 0.145 ms per step at
  * N = 64 on a non-default stream: a graph launch adds a gap before its first
  * kernel).  Stage timings (dse_set_timing) are recorded only with graphs off. */
 dse_status dse_newton_step(dse_ctx* ctx, const double* d_c, double rho, double* d_c_new, double* d_F_new,
